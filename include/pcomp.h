@@ -1,0 +1,128 @@
+/*
+ * pcomp.h -- C ABI of the MI355X (gfx950) polynomial compressor.
+ *
+ * Lossless compression of unsigned integer arrays by the blocked polynomial
+ * method of Aubert et al., "Polynomial data compression for large-scale
+ * physics experiments" (arXiv:1805.01844):
+ *   - the array is cut into blocks of block_len values (Sec. 3.3);
+ *   - each block is reduced to its minimum and base B = max - min + 1 (Sec. 3,
+ *     Sec. 3.1);
+ *   - the digits v - min are packed into 64-bit words by mixed-radix (Horner)
+ *     multiply-add, either the basic way, k = max{k : B^k <= 2^64} digits per
+ *     word (Sec. 3.1, Eqs. (1)-(2)), or the advanced way that splits the last
+ *     base of every word into R_i and R'_i (Sec. 3.2, Eqs. (3)-(11) and the
+ *     series that closes the section);
+ *   - optionally, values at or above a threshold T = 2^(bitlen(B-1) - t) are
+ *     clipped to T in the main digits and their excess is packed separately
+ *     (threshold/excess classes t = 1..7, a value split in the spirit of the
+ *     r / r' split of Sec. 3.2);
+ *   - decompression is the inverse polynomial division (Sec. 3.1), done with
+ *     multiply-high magic-number division.
+ *
+ * Conventions for every entry point:
+ *   - d_* pointers are DEVICE pointers (HBM of the current HIP device), h_*
+ *     pointers are host pointers. The caller allocates and owns every buffer;
+ *     the compress/decompress calls allocate nothing and do not synchronise,
+ *     so they may be captured in a HIP graph.
+ *   - Work is enqueued on `stream` (NULL = the null stream) and completes
+ *     asynchronously; sizes and statuses are written to device memory.
+ *   - Return value: PCOMP_OK, or a negative code for errors found on the host
+ *     before anything is enqueued. Errors found while reading a stream on the
+ *     device are written to *d_status.
+ *   - The library keeps per-device constant tables (digits per word, the
+ *     advanced-method schedule of every base up to 2^16 + 1, magic numbers).
+ *     They are built once per device by pcomp_init() or, failing that, on the
+ *     first call on that device; that one-time set-up is the only allocation
+ *     the library makes.
+ *
+ * Stream format (version 1, little-endian, 8-byte aligned):
+ *   [0,64)    header: u32 magic "PCMP", u16 version, u8 dtype bytes w, u8 flags,
+ *             u8 fixed class, u8 selector, u16 0, u32 block_len L, u64 n,
+ *             u64 n_blocks, u32 tile_blocks, u32 0, u64 payload words,
+ *             u64 total bytes, u64 0
+ *   index     u64 x ceil(n_blocks / tile_blocks): payload word offset of the
+ *             first block of every tile (tiles can be decoded independently)
+ *   min[]     w bytes per block
+ *   range[]   w bytes per block, B - 1
+ *   class[]   u8 per block            (flags bit 0)
+ *   ne[]      u8 per block, u16 if L > 255 (flags bit 1; bit 2 = u16)
+ *   padding to 8 bytes, then the payload: u64 words, block after block.
+ *   tile_blocks = the largest power of two P <= 256 with P * L * w <= 16384.
+ */
+#ifndef PCOMP_H
+#define PCOMP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Element types: the value is the element size in bytes. */
+typedef enum { PCOMP_U8 = 1, PCOMP_U16 = 2, PCOMP_U32 = 4 } pcomp_dtype;
+
+/* Variant argument.
+ *   0..15: one fixed class c = 8 * family + t (family 0 basic, 1 advanced;
+ *          t = 0 plain, t = 1..7 threshold/excess). With t = 0 every block
+ *          uses that class (single-class stream). With t > 0 a block whose
+ *          class is invalid (t > bitlen(B-1)) or not smaller than basic t = 0
+ *          falls back to class 0.
+ *   PCOMP_SELECT_EXHAUSTIVE: per block, the smallest of the 16 classes (ties to
+ *          the lowest id).
+ *   PCOMP_SELECT_LEARNED: per block, the class predicted by the network loaded
+ *          with pcomp_set_model(), kept only if valid and smaller than class 0. */
+#define PCOMP_CLASS(family, t) ((family) * 8 + (t))
+#define PCOMP_SELECT_EXHAUSTIVE 0x100
+#define PCOMP_SELECT_LEARNED 0x200
+
+/* Error codes. */
+#define PCOMP_OK 0
+#define PCOMP_EINVAL (-1)   /* null pointer, bad dtype, block_len 0 or > 65535, bad variant */
+#define PCOMP_ENOSPC (-2)   /* output capacity below pcomp_bound / below n values */
+#define PCOMP_ECORRUPT (-3) /* (device status) stream header or block arrays inconsistent */
+#define PCOMP_ENOMODEL (-4) /* learned selector requested with no model loaded */
+#define PCOMP_EHIP (-5)     /* a HIP runtime call or launch failed */
+#define PCOMP_ENOWS (-6)    /* workspace smaller than pcomp_workspace_size */
+
+/* One-time set-up of the constant tables on the current device. Optional;
+ * thread-safe; returns PCOMP_OK or PCOMP_EHIP. */
+int pcomp_init(void);
+
+/* Host-only, pure. Largest stream the compressor can write for these arguments:
+ * every block is at most its basic t = 0 size, ceil(L_b / (64 / (8 w))) words
+ * (Sec. 3.1, Eq. (1) with B <= 2^(8w)), plus header, index and block arrays.
+ * Returns 0 for invalid arguments. */
+size_t pcomp_bound(uint64_t n, pcomp_dtype dtype, uint32_t block_len, int variant);
+
+/* Host-only, pure. Device workspace bytes that pcomp_compress needs (tile
+ * look-back descriptors and a ticket counter). Returns 0 for invalid args. */
+size_t pcomp_workspace_size(uint64_t n, pcomp_dtype dtype, uint32_t block_len, int variant);
+
+/* Compresses n values of `dtype` at d_in (any alignment of the element type)
+ * in blocks of block_len (the last block holds the remainder) into one v1
+ * stream at d_out (8-byte aligned, out_capacity >= pcomp_bound). The stream
+ * size in bytes is written to *d_out_size (device u64). d_ws must hold
+ * pcomp_workspace_size bytes and be 8-byte aligned; its contents are
+ * overwritten. Calls sharing a workspace must be ordered on one stream. */
+int pcomp_compress(const void *d_in, uint64_t n, pcomp_dtype dtype, uint32_t block_len, int variant,
+                   void *d_out, size_t out_capacity, uint64_t *d_out_size, void *d_ws, size_t ws_bytes,
+                   void *stream);
+
+/* Decompresses the v1 stream at d_in (in_size bytes, 8-byte aligned) into
+ * d_out (capacity out_capacity values of the stream's dtype). *d_status
+ * (device i32) receives PCOMP_OK or PCOMP_ECORRUPT / PCOMP_ENOSPC; on error
+ * the output is unspecified. No workspace is needed. */
+int pcomp_decompress(const void *d_in, size_t in_size, void *d_out, size_t out_capacity, int32_t *d_status,
+                     void *stream);
+
+/* Host-only: reads n, dtype bytes and total stream size from a header that is
+ * already in host memory (first 64 bytes of a stream). Returns PCOMP_OK or
+ * PCOMP_ECORRUPT. */
+int pcomp_stream_info(const void *h_header, uint64_t *n, int *dtype_bytes, uint32_t *block_len,
+                      uint64_t *total_bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PCOMP_H */

@@ -422,14 +422,14 @@ static int choose_class(int variant, int forced, const uint64_t *d, uint64_t n, 
 /*   ne[blocks]    u8 or u16     (flag ORC_F_NE; u16 iff L > 255)           */
 /*   zero padding to a multiple of 8 bytes                                  */
 /*   payload: u64 words, block after block                                  */
-/* tile_blocks = the largest power of two P <= 256 with P * L * w <= 32768, */
+/* tile_blocks = the largest power of two P <= 256 with P * L * w <= 16384, */
 /* at least 1.                                                              */
 /* ---------------------------------------------------------------------- */
 uint32_t orc_tile_blocks(uint32_t L, int w)
 {
     uint64_t per = (uint64_t)L * (uint64_t)w;
     uint32_t P = 256;
-    while (P > 1 && (uint64_t)P * per > 32768u) P >>= 1;
+    while (P > 1 && (uint64_t)P * per > 16384u) P >>= 1;
     return P;
 }
 

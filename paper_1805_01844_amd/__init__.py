@@ -1,0 +1,161 @@
+"""MI355X (gfx950) polynomial lossless compressor -- Python binding.
+
+Thin ctypes marshalling over ``libpcomp.so`` (see ``include/pcomp.h``): every step of
+compression and decompression runs in the library's HIP kernels; PyTorch only
+provides device memory and the current stream. There is no CPU fallback: if the
+library is missing the import of the binding fails.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpcomp.so")
+
+SELECT_EXHAUSTIVE = 0x100
+SELECT_LEARNED = 0x200
+OK, EINVAL, ENOSPC, ECORRUPT, ENOMODEL, EHIP, ENOWS = 0, -1, -2, -3, -4, -5, -6
+_ERR = {EINVAL: "EINVAL", ENOSPC: "ENOSPC", ECORRUPT: "ECORRUPT", ENOMODEL: "ENOMODEL", EHIP: "EHIP",
+        ENOWS: "ENOWS"}
+
+_DT = {torch.uint8: 1, torch.uint16: 2, torch.uint32: 4}
+_TORCH = {1: torch.uint8, 2: torch.uint16, 4: torch.uint32}
+
+_lib = None
+
+
+class PcompError(RuntimeError):
+    def __init__(self, code, what):
+        super().__init__("%s failed: %s (%d)" % (what, _ERR.get(code, "?"), code))
+        self.code = code
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libpcomp.so is not built (run __graft_entry__.build()): " + LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        u64, i32, u32, sz, vp = ctypes.c_uint64, ctypes.c_int, ctypes.c_uint32, ctypes.c_size_t, ctypes.c_void_p
+        L.pcomp_init.restype = i32
+        L.pcomp_init.argtypes = []
+        L.pcomp_bound.restype = sz
+        L.pcomp_bound.argtypes = [u64, i32, u32, i32]
+        L.pcomp_workspace_size.restype = sz
+        L.pcomp_workspace_size.argtypes = [u64, i32, u32, i32]
+        L.pcomp_compress.restype = i32
+        L.pcomp_compress.argtypes = [vp, u64, i32, u32, i32, vp, sz, vp, vp, sz, vp]
+        L.pcomp_decompress.restype = i32
+        L.pcomp_decompress.argtypes = [vp, sz, vp, sz, vp, vp]
+        L.pcomp_stream_info.restype = i32
+        L.pcomp_stream_info.argtypes = [vp, vp, vp, vp, vp]
+        L.pcomp_atlas_info.restype = i32
+        L.pcomp_atlas_info.argtypes = [u64, vp, vp, vp, vp]
+        L.pcomp_atlas_word.restype = i32
+        L.pcomp_atlas_word.argtypes = [u64, u32, vp, vp, vp, vp]
+        _lib = L
+    return _lib
+
+
+def _stream_handle():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _check(rc, what):
+    if rc != OK:
+        raise PcompError(rc, what)
+
+
+def init() -> None:
+    _check(lib().pcomp_init(), "pcomp_init")
+
+
+def bound(n: int, dtype_bytes: int, block_len: int, variant: int) -> int:
+    return lib().pcomp_bound(n, dtype_bytes, block_len, variant)
+
+
+def workspace_size(n: int, dtype_bytes: int, block_len: int, variant: int) -> int:
+    return lib().pcomp_workspace_size(n, dtype_bytes, block_len, variant)
+
+
+class Compressor:
+    """Reusable buffers for repeated compression of same-shaped inputs (no allocation per call)."""
+
+    def __init__(self, n: int, dtype: torch.dtype, block_len: int, variant: int, device="cuda"):
+        self.n, self.w, self.L, self.variant = int(n), _DT[dtype], int(block_len), int(variant)
+        cap = bound(self.n, self.w, self.L, self.variant)
+        if cap == 0:
+            raise PcompError(EINVAL, "pcomp_bound")
+        self.out = torch.empty(cap, dtype=torch.uint8, device=device)
+        self.ws = torch.empty(max(8, workspace_size(self.n, self.w, self.L, self.variant)), dtype=torch.uint8,
+                              device=device)
+        self.size = torch.zeros(1, dtype=torch.int64, device=device)
+
+    def __call__(self, x: torch.Tensor) -> None:
+        """Enqueues compression of x on the current stream (asynchronous)."""
+        assert x.is_cuda and x.numel() == self.n and _DT[x.dtype] == self.w and x.is_contiguous()
+        rc = lib().pcomp_compress(ctypes.c_void_p(x.data_ptr()), self.n, self.w, self.L, self.variant,
+                                  ctypes.c_void_p(self.out.data_ptr()), self.out.numel(),
+                                  ctypes.c_void_p(self.size.data_ptr()), ctypes.c_void_p(self.ws.data_ptr()),
+                                  self.ws.numel(), _stream_handle())
+        _check(rc, "pcomp_compress")
+
+    def stream(self) -> torch.Tensor:
+        """The compressed stream of the last call (synchronises to read its size)."""
+        return self.out[: int(self.size.item())]
+
+
+def compress(x: torch.Tensor, block_len: int, variant: int = 0) -> torch.Tensor:
+    """Compresses a contiguous u8/u16/u32 CUDA tensor; returns the stream as a u8 CUDA tensor."""
+    x = x.contiguous().reshape(-1)
+    c = Compressor(x.numel(), x.dtype, block_len, variant, device=x.device)
+    c(x)
+    return c.stream()
+
+
+def stream_info(stream: torch.Tensor):
+    """(n, dtype bytes, block_len, total bytes) from the stream header."""
+    h = stream[:64].cpu().numpy().tobytes() if stream.is_cuda else bytes(stream[:64].numpy())
+    if len(h) < 64:
+        raise PcompError(ECORRUPT, "pcomp_stream_info")
+    buf = ctypes.create_string_buffer(h, 64)
+    n, w, L, tot = ctypes.c_uint64(), ctypes.c_int(), ctypes.c_uint32(), ctypes.c_uint64()
+    _check(lib().pcomp_stream_info(buf, ctypes.byref(n), ctypes.byref(w), ctypes.byref(L), ctypes.byref(tot)),
+           "pcomp_stream_info")
+    return n.value, w.value, L.value, tot.value
+
+
+def decompress_into(stream: torch.Tensor, out: torch.Tensor, status: torch.Tensor) -> None:
+    """Enqueues decompression into `out` on the current stream (asynchronous); status is i32[1]."""
+    rc = lib().pcomp_decompress(ctypes.c_void_p(stream.data_ptr()), stream.numel(), ctypes.c_void_p(out.data_ptr()),
+                                out.numel(), ctypes.c_void_p(status.data_ptr()), _stream_handle())
+    _check(rc, "pcomp_decompress")
+
+
+def decompress(stream: torch.Tensor) -> torch.Tensor:
+    n, w, L, tot = stream_info(stream)
+    out = torch.empty(max(n, 1), dtype=_TORCH[w], device=stream.device)
+    status = torch.zeros(1, dtype=torch.int32, device=stream.device)
+    decompress_into(stream, out, status)
+    st = int(status.item())
+    if st != OK:
+        raise PcompError(st, "pcomp_decompress (device status)")
+    return out[:n]
+
+
+def atlas_info(B: int):
+    k, mu, lam, V = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
+    _check(lib().pcomp_atlas_info(B, ctypes.byref(k), ctypes.byref(mu), ctypes.byref(lam), ctypes.byref(V)),
+           "pcomp_atlas_info")
+    return k.value, mu.value, lam.value, V.value
+
+
+def atlas_word(B: int, i: int):
+    s, p, R, q = ctypes.c_uint64(), ctypes.c_uint32(), ctypes.c_uint64(), ctypes.c_uint64()
+    _check(lib().pcomp_atlas_word(B, i, ctypes.byref(s), ctypes.byref(p), ctypes.byref(R), ctypes.byref(q)),
+           "pcomp_atlas_word")
+    return s.value, p.value, R.value, q.value

@@ -1,0 +1,106 @@
+// pcomp_internal.h -- shared host/device definitions of the HIP library.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/pcomp.h"
+
+namespace pcomp {
+
+constexpr uint32_t kMagic = 0x504D4350u;  // "PCMP"
+constexpr uint32_t kVersion = 1;
+constexpr uint32_t kHdrBytes = 64;
+constexpr uint32_t kTileBytes = 16384;  // format constant: tile_blocks * L * w <= kTileBytes
+constexpr uint32_t kMaxTileBlocks = 256;
+constexpr uint32_t kThreads = 256;  // threads per workgroup of every kernel
+
+constexpr unsigned kFlagClass = 1, kFlagNe = 2, kFlagNe16 = 4;
+
+// Bases with a precomputed advanced-method schedule: every B in [2, kAtlasDirect]
+// plus 2^j + 1 for j = 17..31 (the main base T + 1 of threshold classes on wide data).
+constexpr uint32_t kAtlasDirect = 65537;
+constexpr uint32_t kAtlasExtra = 15;
+constexpr uint32_t kAtlasBases = kAtlasDirect + 1 + kAtlasExtra;  // indexed by B (0, 1 unused)
+
+// GM magic for unsigned division of a 64-bit dividend by d in [1, 2^32]
+// (Granlund & Montgomery, PLDI 1994, Fig. 4.1):
+//   t = mulhi(m, x); q = (t + ((x - t) >> sh1)) >> sh2.
+struct Magic {
+    uint64_t m;
+    uint32_t sh1, sh2;
+};
+
+// Per-base description of the advanced series (Sec. 3.2). With s_i = R'_{i-1}
+// (s_0 = 1) every word i uses p_i = k if s_i <= Qk else k - 1, R_i = floor(Q_{p_i} / s_i),
+// and the next state is ceil(B / R_i). The state sequence is eventually periodic:
+// s_{i + lam} = s_i for i >= mu, so entries 0 .. mu+lam-1 describe every word.
+struct BaseDesc {
+    uint64_t Qk;   // floor(2^64 / B^k)
+    uint64_t Qk1;  // floor(2^64 / B^(k-1))
+    Magic mB;      // division by B
+    Magic mBp[2];  // division by B^(k-1) and by B^k (the latter unused when B^k = 2^64)
+    uint32_t off;  // first AtlasEntry
+    uint32_t V;    // values consumed by one cycle: q_{mu+lam} - q_mu
+    uint16_t mu, lam;
+    uint32_t k;    // digits per word (basic), k(B) = max{k : B^k <= 2^64}
+};
+
+struct AtlasEntry {
+    Magic mR;     // division by R_i
+    uint32_t s;   // s_i = R'_{i-1}
+    uint32_t R;   // R_i
+    uint32_t q;   // q_i: values consumed before word i
+    uint32_t p;   // p_i
+};
+
+struct DevTables {
+    const BaseDesc *desc;    // [kAtlasBases]
+    const AtlasEntry *ent;   // entries of every base
+    const uint64_t *kmax;    // [65]: kmax[k] = largest B with B^k <= 2^64 (kmax[1] = UINT64_MAX)
+};
+
+// Stream layout (mirrors the format described in pcomp.h).
+struct Layout {
+    uint64_t n, n_blocks, n_tiles;
+    uint32_t L, w, tile_blocks, flags;
+    uint64_t off_index, off_min, off_range, off_class, off_ne, off_payload;
+};
+
+__host__ __device__ inline uint32_t tile_blocks_of(uint32_t L, uint32_t w) {
+    uint64_t per = (uint64_t)L * w;
+    uint32_t P = kMaxTileBlocks;
+    while (P > 1 && (uint64_t)P * per > kTileBytes) P >>= 1;
+    return P;
+}
+
+__host__ __device__ inline unsigned flags_of(int variant, uint32_t L) {
+    if (variant == 0 || variant == 8) return 0;
+    return kFlagClass | kFlagNe | (L > 255 ? kFlagNe16 : 0);
+}
+
+__host__ __device__ inline void make_layout(uint64_t n, uint32_t w, uint32_t L, unsigned flags, Layout &lo) {
+    lo.n = n;
+    lo.L = L;
+    lo.w = w;
+    lo.flags = flags;
+    lo.n_blocks = (n + L - 1) / L;
+    lo.tile_blocks = tile_blocks_of(L, w);
+    lo.n_tiles = (lo.n_blocks + lo.tile_blocks - 1) / lo.tile_blocks;
+    uint64_t o = kHdrBytes;
+    lo.off_index = o;
+    o += 8 * lo.n_tiles;
+    lo.off_min = o;
+    o += (uint64_t)w * lo.n_blocks;
+    lo.off_range = o;
+    o += (uint64_t)w * lo.n_blocks;
+    lo.off_class = o;
+    if (flags & kFlagClass) o += lo.n_blocks;
+    lo.off_ne = o;
+    if (flags & kFlagNe) o += lo.n_blocks * ((flags & kFlagNe16) ? 2 : 1);
+    lo.off_payload = (o + 7) & ~(uint64_t)7;
+}
+
+// Host side: tables of the current device (built on first use).
+int tables_for_current_device(DevTables *out);
+
+}  // namespace pcomp

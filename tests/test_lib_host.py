@@ -1,0 +1,80 @@
+"""Host-only checks of the HIP library (no GPU needed): exports, bounds, the schedule tables."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def pc():
+    import paper_1805_01844_amd as pc
+
+    if not os.path.exists(pc.LIB_PATH):
+        from paper_1805_01844_amd import build
+
+        build.build()
+    pc.lib()
+    return pc
+
+
+def _declared_functions():
+    names = []
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", fn)).read()
+            src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+            names += re.findall(r"\b(pcomp_[a-z_0-9]+)\s*\(", src)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_function(pc):
+    names = _declared_functions()
+    assert "pcomp_compress" in names and "pcomp_decompress" in names and "pcomp_bound" in names
+    L = ctypes.CDLL(pc.LIB_PATH)
+    for name in names:
+        assert hasattr(L, name), name
+
+
+@pytest.mark.parametrize("w,L", [(1, 1), (1, 1024), (2, 40), (2, 1024), (4, 256), (4, 4096), (2, 65535)])
+@pytest.mark.parametrize("variant", [0, 8, 3, 0x100, 0x200])
+def test_bound_matches_oracle(pc, orc, w, L, variant):
+    for n in [0, 1, L - 1, L, 10 * L + 3, 123457]:
+        assert pc.bound(n, w, L, variant) == orc.bound(n, w, L, variant)
+        assert pc.workspace_size(n, w, L, variant) >= 8
+
+
+def test_bound_rejects_bad_arguments(pc):
+    assert pc.bound(10, 3, 40, 0) == 0
+    assert pc.bound(10, 2, 0, 0) == 0
+    assert pc.bound(10, 2, 65536, 0) == 0
+    assert pc.bound(10, 2, 40, 16) == 0
+
+
+def test_schedule_tables_match_oracle_series(pc, orc):
+    # the cycle form of every tabled base reproduces the oracle's series word by word
+    rng = np.random.default_rng(0)
+    bases = list(range(2, 300)) + [int(b) for b in rng.integers(300, 65538, 300)] + [65535, 65536, 65537]
+    bases += [(1 << j) + 1 for j in range(17, 32)]
+    for B in bases:
+        n = 4000 if B < 65538 else 300
+        p, R, Rp, q = orc.adv_schedule(n, B)
+        k, mu, lam, V = pc.atlas_info(B)
+        assert k == orc.digits_per_word(B)
+        if B > 65537:
+            continue
+        for i in range(len(p)):
+            s_i, p_i, R_i, q_i = pc.atlas_word(B, i)
+            assert (s_i, p_i, R_i, q_i) == (int(Rp[i]), int(p[i]), int(R[i]), int(q[i])), (B, i)
+
+
+def test_schedule_cycles_are_short(pc):
+    worst = 0
+    for B in range(2, 65538, 7):
+        k, mu, lam, V = pc.atlas_info(B)
+        worst = max(worst, mu + lam)
+        assert lam >= 1 and V > 0
+    assert worst < 600
