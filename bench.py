@@ -1,0 +1,200 @@
+"""Benchmark of the polynomial compressor on one MI355X.
+
+One step = the whole hot path over one batch: compress (block min/max, class choice,
+placement, packing) and decompress (unpacking) of camera-shaped synthetic waveforms,
+10,000 events x 1855 pixels x 40 samples of u16 (1.484 GB), one block per pixel trace
+(block_len = 40), per-block exhaustive choice over the 16 classes. Inputs are resident in
+HBM before timing starts. After the timed steps the round trip is checked bit for bit.
+
+Prints ONE JSON line. `value` is round-trip throughput: uncompressed bytes per step over
+(compress + decompress) time; compress and decompress GB/s are reported separately.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBPS = 8000.0  # MI355X HBM3E
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--events", type=int, default=10000)
+    ap.add_argument("--variant", default="exhaustive", help="exhaustive | learned | class id 0..15")
+    ap.add_argument("--block-len", type=int, default=40)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU work of the baseline sample")
+    return ap.parse_args()
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1805_01844_amd", "csrc")
+    for fn in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, fn), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(kernel: str, launches_bytes: float):
+    """HBM bytes per launch from the committed counter summary, if taken on the current kernels."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("source_hash") != kernel_source_hash() or kernel not in t.get("kernels", {}):
+        return None
+    return t["kernels"][kernel]["hbm_bytes_per_launch"]
+
+
+def cpu_baseline(x_host_events, variant: int, L: int, seconds: float):
+    """The CPU oracle as it stands, on a bounded sample of the same workload, one stream per
+    event chunk, host threads in parallel (ctypes releases the GIL)."""
+    import concurrent.futures as cf
+
+    import numpy as np
+
+    import oracle
+
+    oracle.lib()
+    cores = min(16, os.cpu_count() or 1)
+    ev = x_host_events
+    # calibrate on one event, then size the sample to about `seconds` of work
+    t0 = time.perf_counter()
+    s = oracle.compress(ev[0].reshape(-1), L, variant)
+    oracle.decompress(s)
+    per_event = time.perf_counter() - t0
+    n_ev = int(max(cores, seconds * cores / max(per_event, 1e-6)))
+    chunks = [ev[i % len(ev)].reshape(-1) for i in range(n_ev)]
+
+    def work(a):
+        st = oracle.compress(a, L, variant)
+        b = oracle.decompress(st)
+        assert np.array_equal(a, b)
+        return len(st)
+
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(cores) as pool:
+        sizes = list(pool.map(work, chunks))
+    dt = time.perf_counter() - t0
+    nbytes = sum(c.nbytes for c in chunks)
+    return {"value": nbytes / dt / 1e9, "unit": "GB/s", "cores": cores, "kind": "oracle",
+            "sample": "%d events cycled from the first %d of the workload (%.1f MB), compress+decompress "
+                      "round trip, one stream per event" % (n_ev, len(ev), nbytes / 1e6),
+            "ratio": nbytes / sum(sizes)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build runs on a single MI355X (--gpus 1).", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import datagen
+    import paper_1805_01844_amd as pc
+
+    variant = {"exhaustive": pc.SELECT_EXHAUSTIVE, "learned": pc.SELECT_LEARNED}.get(args.variant)
+    if variant is None:
+        variant = int(args.variant)
+    L = args.block_len
+    dev = torch.device("cuda:0")
+    pc.init()
+    x = datagen.camera_events(args.events, seed=1, device=dev)
+    torch.cuda.synchronize()
+    xf = x.reshape(-1)
+    n = xf.numel()
+    nbytes = n * 2
+    comp = pc.Compressor(n, torch.uint16, L, variant, device=dev)
+    out = torch.empty(n, dtype=torch.uint16, device=dev)
+    status = torch.zeros(1, dtype=torch.int32, device=dev)
+
+    # one untimed pass to learn the stream size
+    comp(xf)
+    stream_len = int(comp.size.item())
+    stream = comp.out[:stream_len]
+
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3 * (args.steps + args.warmup))]
+    for i in range(args.warmup):
+        comp(xf)
+        pc.decompress_into(stream, out, status)
+    torch.cuda.synchronize()
+    t_c, t_d = [], []
+    wall0 = time.perf_counter()
+    for i in range(args.steps):
+        e0, e1, e2 = ev[3 * i], ev[3 * i + 1], ev[3 * i + 2]
+        e0.record()
+        comp(xf)
+        e1.record()
+        pc.decompress_into(stream, out, status)
+        e2.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    for i in range(args.steps):
+        t_c.append(ev[3 * i].elapsed_time(ev[3 * i + 1]) / 1e3)
+        t_d.append(ev[3 * i + 1].elapsed_time(ev[3 * i + 2]) / 1e3)
+    tc, td = float(np.mean(t_c)), float(np.mean(t_d))
+    # checks after the timed region: bit-exact round trip, stable stream size
+    assert int(status.item()) == 0, "decompress status %d" % int(status.item())
+    assert int(comp.size.item()) == stream_len
+    assert torch.equal(out.view(torch.int16), xf.view(torch.int16)), "round trip is not bit-exact"
+
+    comp_gbps = nbytes / tc / 1e9
+    dec_gbps = nbytes / td / 1e9
+    value = nbytes / (tc + td) / 1e9
+    ratio = nbytes / stream_len
+    # dominant kernel: algorithmic bytes = what it must read + what it must write
+    kern = "compress_kernel" if tc >= td else "decompress_kernel"
+    alg = (nbytes + stream_len) if kern == "compress_kernel" else (stream_len + nbytes)
+    dur = max(tc, td)
+    achieved = alg / dur / 1e9
+    traffic = traffic_from_profiles(kern, alg)
+    res = {
+        "metric": "compress/decompress GB/s on 1 MI355X, bit-exact round-trip; compression ratio",
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round((tc + td) * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u16",
+        "data": "synthetic",
+        "config": {
+            "workload": "camera waveforms: %d events x 1855 px x 40 samples u16 (%.3f GB), block = one pixel "
+                        "trace (L=%d), %s class choice" % (args.events, nbytes / 1e9, L, args.variant),
+            "events": args.events, "block_len": L, "variant": args.variant,
+        },
+        "compress_GBps": round(comp_gbps, 2),
+        "decompress_GBps": round(dec_gbps, 2),
+        "ratio": round(ratio, 4),
+        "stream_bytes": stream_len,
+        "roundtrip_bit_exact": True,
+        "wall_s_timed": round(wall, 4),
+        "roofline": {"bound": "hbm", "kernel": kern, "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS,
+                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBPS, 4), "traffic": traffic,
+                     "algorithmic_bytes_per_launch": alg},
+    }
+    if not args.no_cpu:
+        xe = x[: min(args.events, 256)].cpu().view(torch.int16).numpy().view(np.uint16)
+        res["cpu_baseline"] = cpu_baseline(xe, variant if variant != pc.SELECT_LEARNED else 0x100, L,
+                                           args.cpu_seconds)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

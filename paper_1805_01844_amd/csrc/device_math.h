@@ -119,6 +119,7 @@ __device__ inline uint32_t adv_words_slow(const SlowBase &sb, uint32_t n) {
 // Word count of the series from the cycle form: c_t = q_t + p_t grows with t, and
 // c_{t + lam} = c_t + V for t >= mu; the count is 1 + the first t with c_t >= n.
 __device__ inline uint32_t adv_words_atlas(const DevTables &T, const BaseDesc &D, uint32_t n) {
+    if (n <= D.k) return 1;  // the first word holds k digits (s_0 = 1)
     const AtlasEntry *E = T.ent + D.off;
     uint32_t tot = D.mu + D.lam;
     uint32_t clast = E[tot - 1].q + E[tot - 1].p;

@@ -103,6 +103,44 @@ __device__ inline uint32_t class_words(const DevTables &T, int c, uint32_t Lb, u
     return nw_main + family_words(T, fam, ne_t, B - Th);
 }
 
+// Per-workgroup cache for the main part of threshold classes: base 2^j + 1 (j = beta - t),
+// digits per word and advanced word count of a full block of L digits.
+struct P1Cache {
+    uint32_t k[32];
+    uint32_t adv_full[32];
+};
+
+__device__ inline void fill_p1_cache(const DevTables &T, uint32_t L, P1Cache &C) {
+    const uint32_t j = threadIdx.x;
+    if (j < 32) {
+        const uint64_t base = (1ull << j) + 1;
+        const int ai = atlas_index(base);
+        C.k[j] = T.desc[ai].k;
+        C.adv_full[j] = adv_words_atlas(T, T.desc[ai], L);
+    }
+}
+
+__device__ __forceinline__ uint32_t words_p1(const DevTables &T, const P1Cache &C, int fam, uint32_t j, uint32_t n,
+                                             uint32_t L) {
+    if (!fam) return (n + C.k[j] - 1) / C.k[j];
+    if (n == L) return C.adv_full[j];
+    return adv_words_atlas(T, T.desc[atlas_index((1ull << j) + 1)], n);
+}
+
+// class_words with the main part of threshold classes served from the cache.
+__device__ inline uint32_t class_words_c(const DevTables &T, const P1Cache &C, uint32_t L, int c, uint32_t Lb,
+                                         uint64_t B, uint32_t beta, uint32_t ne_t, uint32_t &nw_main) {
+    int fam = c >> 3, t = c & 7;
+    if (t == 0) {
+        nw_main = family_words(T, fam, Lb, B);
+        return nw_main;
+    }
+    const uint32_t j = beta - t;
+    const uint64_t Th = 1ull << j;
+    nw_main = words_p1(T, C, fam, j, Lb, L);
+    return nw_main + family_words(T, fam, ne_t, B - Th);
+}
+
 // Resolved description of one packed part of a block (main digits or excess list).
 struct Part {
     uint64_t base;
@@ -175,11 +213,13 @@ __global__ __launch_bounds__(kThreads) void compress_kernel(CompressArgs a) {
     __shared__ uint32_t s_red32[kThreads / 64];
     __shared__ uint32_t s_tile;
     __shared__ uint64_t s_excl;
+    __shared__ P1Cache s_p1;
 
     const Layout &lo = a.lo;
     const DevTables &T = a.T;
     const uint32_t tid = threadIdx.x;
     if (tid == 0) s_tile = atomicAdd(a.ticket, 1u);
+    if (a.variant != 0 && a.variant != 8) fill_p1_cache(T, lo.L, s_p1);
     __syncthreads();
     const uint32_t tile = s_tile;
     if (lo.n_tiles == 0) {
@@ -265,7 +305,7 @@ __global__ __launch_bounds__(kThreads) void compress_kernel(CompressArgs a) {
             int t = c & 7;
             if (t > (int)beta) continue;
             uint32_t nwm;
-            uint32_t nw = class_words(T, c, Lb, B, beta, ne_t[t], nwm);
+            uint32_t nw = class_words_c(T, s_p1, L, c, Lb, B, beta, ne_t[t], nwm);
             uint64_t k2 = ((uint64_t)nw << 8) | (uint64_t)c;
             key = k2 < key ? k2 : key;
         }
@@ -286,7 +326,10 @@ __global__ __launch_bounds__(kThreads) void compress_kernel(CompressArgs a) {
     const uint64_t Th = tcls ? (1ull << (beta - tcls)) : 0;
     if (live && g == 0) {
         uint32_t nwm;
-        class_words(T, cls, Lb, B, beta, ne_t[tcls], nwm);
+        if (fixed0)
+            nwm = nw;
+        else
+            class_words_c(T, s_p1, L, cls, Lb, B, beta, ne_t[tcls], nwm);
         s_min[blk] = vmin;
         s_rng[blk] = (uint32_t)(B - 1);
         s_cls[blk] = (uint8_t)cls;
@@ -344,39 +387,55 @@ __global__ __launch_bounds__(kThreads) void compress_kernel(CompressArgs a) {
     }
     const uint32_t tile_words = s_off[nbt];
 
-    // ---- 6. decoupled look-back: exclusive prefix of the payload words of earlier tiles
-    if (tid == 0) {
-        uint64_t excl = 0;
+    // ---- 6. decoupled look-back: exclusive prefix of the payload words of earlier tiles.
+    // The first wavefront reads 64 predecessors' descriptors at once; lanes up to the
+    // nearest inclusive prefix must all be published, their values are summed, and the
+    // window moves back by 64 tiles while no inclusive prefix is in sight.
+    if (tid < 64) {
+        const uint32_t lane = tid;
         if (tile == 0) {
-            __hip_atomic_store(&a.tile_status[0], kStInc | tile_words, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            __hip_atomic_store(&a.tile_status[tile], kStAgg | tile_words, __ATOMIC_RELEASE,
-                               __HIP_MEMORY_SCOPE_AGENT);
-            int64_t j = (int64_t)tile - 1;
-            uint32_t spins = 0;
-            while (j >= 0) {
-                uint64_t st = __hip_atomic_load(&a.tile_status[j], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-                if (st & kStInc) {
-                    excl += st & kStMask;
-                    break;
-                }
-                if (st & kStAgg) {
-                    excl += st & kStMask;
-                    j--;
-                    continue;
-                }
-                if (++spins > (1u << 26)) {  // a predecessor never published: flag and give up
-                    atomicOr(a.err, 1u);
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(1);
-            }
-            __hip_atomic_store(&a.tile_status[tile], kStInc | (excl + tile_words), __ATOMIC_RELEASE,
+            if (lane == 0)
+                __hip_atomic_store(&a.tile_status[0], kStInc | tile_words, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+        } else if (lane == 0) {
+            __hip_atomic_store(&a.tile_status[tile], kStAgg | tile_words, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
         }
-        s_excl = excl;
-        put_le(a.out + lo.off_index + 8 * (uint64_t)tile, excl, 8);
-        if (tile == lo.n_tiles - 1) write_header(a, excl + tile_words, variant);
+        uint64_t excl = 0;
+        if (tile > 0) {
+            int64_t top = (int64_t)tile - 1;
+            uint32_t spins = 0;
+            for (;;) {
+                const int64_t j = top - (int64_t)lane;
+                uint64_t st = kStInc;  // before tile 0: an inclusive prefix of 0
+                if (j >= 0) st = __hip_atomic_load(&a.tile_status[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const uint64_t inc_mask = __ballot((st & kStInc) != 0);
+                const uint64_t nr_mask = __ballot((st & (kStInc | kStAgg)) == 0);
+                const uint32_t first = inc_mask ? (uint32_t)(__ffsll((unsigned long long)inc_mask) - 1) : 64u;
+                const uint64_t need = first >= 63 ? ~0ull : ((2ull << first) - 1);
+                if (nr_mask & need) {
+                    if (++spins > (1u << 24)) {  // a predecessor never published: flag it and stop
+                        if (lane == 0) atomicOr(a.err, 1u);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                    continue;
+                }
+                uint64_t v = lane <= first ? (st & kStMask) : 0;
+                for (uint32_t o = 1; o < 64; o <<= 1) v += __shfl_xor(v, o, 64);
+                excl += v;
+                if (first < 64 || top < 64) break;  // top < 64: the window reached tile 0
+                top -= 64;
+            }
+            if (lane == 0)
+                __hip_atomic_store(&a.tile_status[tile], kStInc | (excl + tile_words), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+        }
+        if (lane == 0) {
+            s_excl = excl;
+            put_le(a.out + lo.off_index + 8 * (uint64_t)tile, excl, 8);
+            if (tile == lo.n_tiles - 1) write_header(a, excl + tile_words, variant);
+        }
     }
     __syncthreads();
     const uint64_t excl = s_excl;
@@ -575,11 +634,6 @@ __device__ void decompress_tiles(const DecompressArgs &a, const Layout &lo, uint
             s_nwm[tid] = nwm;
             s_off[tid] = nw;
         }
-        // zero the digit buffers (blocks with B = 1 or a base-1 excess list have no words)
-        for (uint32_t c = tid; c < kTileBytes / 16; c += kThreads) {
-            s_raw[c] = make_uint4(0, 0, 0, 0);
-            s_exc_raw[c] = make_uint4(0, 0, 0, 0);
-        }
         __syncthreads();
         {
             uint32_t x = tid < nbt ? s_off[tid] : 0;
@@ -747,10 +801,12 @@ __device__ void decompress_tiles(const DecompressArgs &a, const Layout &lo, uint
             }
             if (t) {
                 const uint32_t ne = s_ne[blk];
+                // a base-1 excess list (B - T = 1) has no words: every excess is 0
+                const bool exc_words = (uint64_t)s_rng[blk] + 1 - Tb > 1;
                 for (uint32_t j = j0; j < j1; j++) {
                     uint32_t d = vals[j];
                     if (d == Tb) {
-                        d = Tb + (pos < ne ? (uint32_t)ex[pos] : 0u);
+                        d = Tb + ((exc_words && pos < ne) ? (uint32_t)ex[pos] : 0u);
                         pos++;
                     }
                     vals[j] = (V)(d + bmin);
