@@ -104,9 +104,17 @@ class Compressor:
                                   self.ws.numel(), _stream_handle())
         _check(rc, "pcomp_compress")
 
+    def error_flag(self) -> int:
+        """Internal error word of the last call (0 = none; synchronises)."""
+        return int(self.ws[:4].view(torch.int32).item())
+
     def stream(self) -> torch.Tensor:
         """The compressed stream of the last call (synchronises to read its size)."""
-        return self.out[: int(self.size.item())]
+        n = int(self.size.item())
+        err = self.error_flag()
+        if err:
+            raise PcompError(EHIP, "pcomp_compress (device error word %d)" % err)
+        return self.out[:n]
 
 
 def compress(x: torch.Tensor, block_len: int, variant: int = 0) -> torch.Tensor:

@@ -16,6 +16,7 @@
 #include <unordered_map>
 #include <vector>
 
+#include "device_math.h"
 #include "pcomp_internal.h"
 
 namespace pcomp {
@@ -42,6 +43,25 @@ Magic magic_host(uint64_t d) {
     return mg;
 }
 
+Chunk chunk_host(uint64_t B) {
+    Chunk c{};
+    if (B >= (1ull << 24)) return c;  // h = 0
+    uint64_t P = 1;
+    uint32_t h = 0;
+    while (P * B < (1ull << 32) && P < (1ull << 24)) {  // keeps B^h < 2^32 and B^(h-1) < 2^24
+        P *= B;
+        h++;
+    }
+    c.h = h;
+    c.P = (uint32_t)P;
+    c.mP = magic_host(P);
+    uint32_t l = 0;
+    while ((1ull << l) < B) l++;
+    c.m32 = (uint32_t)((((1ull << l) - B) << 32) / B) + 1;
+    c.sh32 = l - 1;
+    return c;
+}
+
 uint32_t k_host(uint64_t B) {
     u128 acc = 1;
     uint32_t k = 0;
@@ -62,6 +82,7 @@ void build_base(uint64_t B, BaseDesc &D, std::vector<AtlasEntry> &ent) {
     D.Qk = (uint64_t)(kTwo64 / bk);
     D.mBp[1] = magic_host(bk < kTwo64 ? (uint64_t)bk : 1);
     D.mB = magic_host(B);
+    D.ch = chunk_host(B);
     D.off = (uint32_t)ent.size();
     std::unordered_map<uint64_t, uint32_t> seen;
     uint64_t s = 1;
@@ -206,5 +227,22 @@ extern "C" int pcomp_atlas_word(uint64_t B, uint32_t i, uint64_t *s, uint32_t *p
     *p = e->p;
     *R = e->R;
     *q = qq;
+    return PCOMP_OK;
+}
+
+// Host-side: advanced word count of n digits of base B computed from the cycle form.
+extern "C" int pcomp_atlas_words(uint64_t B, uint32_t n, uint32_t *words) {
+    using namespace pcomp;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        build_host_tables();
+    }
+    int idx = -1;
+    if (B >= 2 && B <= kAtlasDirect) idx = (int)B;
+    for (uint32_t j = 17; j <= 31; j++)
+        if (B == (1ull << j) + 1) idx = (int)(kAtlasDirect + 1 + (j - 17));
+    if (idx < 0 || n == 0) return PCOMP_EINVAL;
+    const BaseDesc &D = (*g_desc)[idx];
+    *words = adv_words_cycle(g_ent->data() + D.off, D, n);
     return PCOMP_OK;
 }

@@ -1,0 +1,322 @@
+// decompress.hip -- grid-stride decompression kernel (gfx950).
+//
+// The stream's tile index gives every tile its payload offset, so tiles decode
+// independently. Per tile: the block arrays are read into LDS and every block's word count
+// is recomputed from (L_b, B, class, n_e); the lanes of a block's group decode its words in
+// turn, peeling digits from the lowest power by multiply-high magic-number division (the
+// inverse polynomial division of Sec. 3.1); for the advanced method the value split
+// between word i (r_i) and word i+1 (r'_i on top) is rebuilt by the lane of word i from
+// both words; threshold blocks merge their excess list back in data order; the tile leaves
+// LDS through coalesced stores.
+#include "kernels_common.h"
+
+namespace pcomp {
+
+struct DecompressArgs {
+    const uint8_t *in;
+    uint64_t in_size;
+    uint8_t *out;
+    uint64_t out_cap;
+    int32_t *status;
+    DevTables T;
+};
+
+__device__ __forceinline__ void set_status(int32_t *st, int32_t code) { atomicMin(st, code); }
+
+// Reads and checks the stream header; returns false if it is unusable.
+__device__ bool read_layout(const DecompressArgs &a, Layout &lo, uint64_t &pw, int &fixed) {
+    if (a.in_size < kHdrBytes) return false;
+    const uint64_t *h = (const uint64_t *)a.in;
+    const uint64_t h0 = h[0], h1 = h[1];
+    if ((uint32_t)h0 != kMagic || ((h0 >> 32) & 0xFFFF) != kVersion) return false;
+    const uint32_t w = (uint32_t)((h0 >> 48) & 0xFF), flags = (uint32_t)(h0 >> 56);
+    if (!(w == 1 || w == 2 || w == 4) || (flags & ~7u)) return false;
+    fixed = (int)(h1 & 0xFF);
+    const uint32_t L = (uint32_t)(h1 >> 32);
+    if (L == 0 || L > 65535) return false;
+    if (!(flags & kFlagClass) && !(fixed == 0 || fixed == 8)) return false;
+    if ((flags & kFlagNe) && (((flags & kFlagNe16) != 0) != (L > 255))) return false;
+    make_layout(h[2], w, L, flags, lo);
+    if (h[3] != lo.n_blocks || (uint32_t)h[4] != lo.tile_blocks) return false;
+    pw = h[5];
+    if (pw > (a.in_size >> 3) || h[6] != lo.off_payload + 8 * pw || h[6] > a.in_size) return false;
+    return true;
+}
+
+struct DecShared {
+    uint4 raw[kTileBytes / 16];  // decoded digits / values of the tile
+    uint4 exc[kTileBytes / 16];  // decoded excess lists
+    uint32_t min[kMaxTileBlocks], rng[kMaxTileBlocks], ne[kMaxTileBlocks];
+    uint32_t nwm[kMaxTileBlocks], off[kMaxTileBlocks + 1];
+    uint8_t cls[kMaxTileBlocks];
+    uint32_t red32[kThreads / 64];
+    int bad;
+    SizeCtx C;
+};
+
+// Advanced part whose base is outside the tables: one lane walks the series word by word
+// (kept out of line: it is rare and register-hungry).
+template <typename V>
+__device__ __forceinline__ void unpack_adv_slow(const DevTables &T, uint64_t base, uint32_t n, uint32_t nwords,
+                                             const uint64_t *src, V *dst, uint32_t add) {
+    const SlowBase sb = slow_base(T, base);
+    const Magic mB = magic_dev(base);
+    uint64_t s = 1, r_prev = 0, R_prev = 1;
+    uint32_t q = 0, q_prev = 0, p_prev = 0;
+    for (uint32_t wi = 0; wi < nwords; wi++) {
+        uint32_t p;
+        uint64_t R;
+        slow_word(sb, s, p, R);
+        uint64_t X = src[wi];
+        const uint64_t qR = X / R;
+        const uint64_t r = X - qR * R;
+        X = qR;
+        for (int j = (int)p - 1; j >= 0; j--) {
+            const uint64_t qq = div_magic(X, mB);
+            const uint32_t d = (uint32_t)(X - qq * base);
+            X = qq;
+            if (q + j < n) dst[q + j] = (V)(d + add);
+        }
+        if (wi > 0 && q_prev + p_prev < n) dst[q_prev + p_prev] = (V)(X * R_prev + r_prev + add);
+        if (q + p >= n) break;
+        r_prev = r;
+        R_prev = R;
+        q_prev = q;
+        p_prev = p;
+        s = (base + R - 1) / R;
+        q += p + 1;
+    }
+}
+
+// Decodes words i0, i0+G, ... of one part (main digits or excess list) into dst[0 .. n);
+// `add` is added to every digit (the block minimum for plain blocks).
+template <typename V>
+__device__ __forceinline__ void unpack_part(const DevTables &T, const SizeCtx &C, uint64_t base, uint32_t n, int fam,
+                                            uint32_t nwords, uint32_t i0, uint32_t G, const uint64_t *src, V *dst,
+                                            uint32_t add) {
+    if (nwords == 0 || i0 >= nwords) return;
+    const PartBase pb = resolve_base(T, C, base);
+    auto put = [&](uint32_t j, uint32_t d) {
+        if (j < n) dst[j] = (V)(d + add);
+    };
+    if (!fam) {
+        // inverse of Sec. 3.1 Eq. (2): the k digits of word i, peeled from the lowest power
+        for (uint32_t i = i0; i < nwords; i += G) peel_digits(pb, src[i], i * pb.k, pb.k, put);
+        return;
+    }
+    if (pb.D) {
+        const BaseDesc &D = *pb.D;
+        for (uint32_t i = i0; i < nwords; i += G) {
+            uint32_t q;
+            const AtlasEntry *e = adv_entry(T, D, i, q);
+            const uint64_t X = src[i];
+            const uint64_t qR = div_magic(X, e->mR);
+            const uint64_t r = X - qR * e->R;  // r_i, the low part of the split value
+            const uint32_t p = e->p;
+            peel_digits(pb, qR, q, p, put);  // what remains on top is r'_{i-1}
+            // the value split between this word (r_i at the bottom) and the next (r'_i on top)
+            if (q + p < n && i + 1 < nwords) {
+                uint32_t q1;
+                const AtlasEntry *e1 = adv_entry(T, D, i + 1, q1);
+                const uint64_t Y = div_magic(src[i + 1], e1->mR);
+                const uint64_t rp = div_magic(Y, D.mBp[e1->p == D.k ? 1 : 0]);
+                put(q + p, (uint32_t)(rp * e->R + r));
+            }
+        }
+        return;
+    }
+    // base outside the tables: the group's first lane walks the series over the whole part
+    if (i0 == 0) unpack_adv_slow<V>(T, base, n, nwords, src, dst, add);
+}
+
+template <int W>
+__device__ void decompress_tiles(const DecompressArgs &a, const Layout &lo, uint64_t pw, int fixed, DecShared &S) {
+    typedef typename Elem<W>::T V;
+    const DevTables &T = a.T;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t L = lo.L, tb = lo.tile_blocks;
+    const uint32_t G = kThreads / tb;
+    const uint64_t *idx = (const uint64_t *)(a.in + lo.off_index);
+    const uint64_t *payload_all = (const uint64_t *)(a.in + lo.off_payload);
+    const uint64_t vmaxw = (1ull << (8 * W)) - 1;
+    V *s_val = (V *)S.raw;
+    V *s_exc = (V *)S.exc;
+    const int neb = (lo.flags & kFlagNe16) ? 2 : 1;
+
+    for (uint64_t tile = blockIdx.x; tile < lo.n_tiles; tile += gridDim.x) {
+        const uint64_t b0 = tile * tb;
+        const uint32_t nbt = (uint32_t)min((uint64_t)tb, lo.n_blocks - b0);
+        const uint64_t v0 = b0 * L;
+        const uint32_t nvt = (uint32_t)min((uint64_t)nbt * L, lo.n - v0);
+        if (tid == 0) S.bad = 0;
+        __syncthreads();
+        // ---- 1. block arrays of the tile and word counts (the tile's index entries are
+        //         fetched at once, alongside)
+        const uint64_t base_off = idx[tile];
+        const uint64_t next_off = (tile + 1 < lo.n_tiles) ? idx[tile + 1] : pw;
+        uint32_t nw = 0;
+        if (tid < nbt) {
+            const uint64_t gb = b0 + tid;
+            const uint32_t bmin = (uint32_t)get_le(a.in + lo.off_min + gb * W, W);
+            const uint32_t rng = (uint32_t)get_le(a.in + lo.off_range + gb * W, W);
+            const int c = (lo.flags & kFlagClass) ? a.in[lo.off_class + gb] : fixed;
+            const uint32_t ne = (lo.flags & kFlagNe) ? (uint32_t)get_le(a.in + lo.off_ne + gb * neb, neb) : 0;
+            const uint32_t Lb = (uint32_t)min((uint64_t)L, lo.n - gb * L);
+            const uint64_t B = (uint64_t)rng + 1;
+            const uint32_t beta = bitlen64(B - 1);
+            const int t = c & 7;
+            const bool ok = c < 16 && t <= (int)beta && ne <= Lb && (t != 0 || ne == 0) && (uint64_t)bmin + rng <= vmaxw;
+            uint32_t nwm = 0;
+            if (ok) nw = class_words(T, S.C, L, c, Lb, B, beta, ne, nwm);
+            if (!ok) S.bad = 1;
+            S.min[tid] = bmin;
+            S.rng[tid] = rng;
+            S.cls[tid] = (uint8_t)(ok ? c : 0);
+            S.ne[tid] = ne;
+            S.nwm[tid] = nwm;
+        }
+        uint32_t tile_words;
+        const uint32_t ex = wg_excl_scan(nw, S.red32, &tile_words);
+        if (tid < nbt) S.off[tid] = ex;
+        if (tid == 0) S.off[nbt] = tile_words;
+        __syncthreads();
+        if (S.bad || base_off > pw || next_off > pw || next_off != base_off + tile_words) {
+            if (tid == 0) set_status(a.status, PCOMP_ECORRUPT);
+            __syncthreads();
+            continue;
+        }
+        const uint64_t *payload = payload_all + base_off;
+
+        // ---- 2. decode: the lanes of a block's group take its words in turn
+        const uint32_t blk = tid / G, g = tid % G;
+        const bool live = blk < nbt;
+        if (live) {
+            const uint32_t nwb = S.off[blk + 1] - S.off[blk];
+            const int c = S.cls[blk];
+            const int t = c & 7, fam = c >> 3;
+            const uint64_t B = (uint64_t)S.rng[blk] + 1;
+            const uint32_t Lb = (uint32_t)min((uint64_t)L, lo.n - (b0 + blk) * L);
+            const uint64_t *src = payload + S.off[blk];
+            V *vals = s_val + (size_t)blk * L;
+            if (t == 0) {
+                unpack_part<V>(T, S.C, B, Lb, fam, nwb, g, G, src, vals, S.min[blk]);
+            } else {
+                const uint64_t Th = 1ull << (bitlen64(B - 1) - t);
+                const uint32_t nwm = S.nwm[blk];
+                unpack_part<V>(T, S.C, Th + 1, Lb, fam, nwm, g, G, src, vals, 0);
+                unpack_part<V>(T, S.C, B - Th, S.ne[blk], fam, nwb - nwm, g, G, src + nwm, s_exc + (size_t)blk * L, 0);
+            }
+        }
+        __syncthreads();
+
+        // ---- 3. threshold blocks: a main digit equal to T marks the next excess value; add min.
+        //         Blocks with B = 1 have no words: every value is the minimum.
+        {
+            const int c = live ? S.cls[blk] : 0;
+            const int t = c & 7;
+            const uint32_t Lb = live ? (uint32_t)min((uint64_t)L, lo.n - (b0 + blk) * L) : 0;
+            const uint32_t ch = (Lb + G - 1) / G;
+            const uint32_t j0 = g * ch < Lb ? g * ch : Lb, j1 = (g + 1) * ch < Lb ? (g + 1) * ch : Lb;
+            V *vals = s_val + (size_t)blk * L;
+            uint32_t Tb = 0;
+            uint32_t cnt = 0;
+            if (t) {
+                Tb = 1u << (bitlen64((uint64_t)S.rng[blk]) - t);
+                for (uint32_t j = j0; j < j1; j++) cnt += (uint32_t)vals[j] == Tb;
+            }
+            uint32_t pos = group_excl_scan(cnt, G, S.red32);
+            if (live && !t && S.rng[blk] == 0) {
+                const V m = (V)S.min[blk];
+                for (uint32_t j = j0; j < j1; j++) vals[j] = m;
+            }
+            if (t) {
+                const uint32_t ne = S.ne[blk];
+                const uint32_t bmin = S.min[blk];
+                const bool exc_words = (uint64_t)S.rng[blk] + 1 - Tb > 1;  // else every excess is 0
+                const V *ex = s_exc + (size_t)blk * L;
+                for (uint32_t j = j0; j < j1; j++) {
+                    uint32_t d = vals[j];
+                    if (d == Tb) {
+                        d = Tb + ((exc_words && pos < ne) ? (uint32_t)ex[pos] : 0u);
+                        pos++;
+                    }
+                    vals[j] = (V)(d + bmin);
+                }
+            }
+        }
+        __syncthreads();
+
+        // ---- 4. coalesced store of the tile (16-byte stores where the output is aligned)
+        {
+            const uint8_t *sb = (const uint8_t *)S.raw;
+            uint8_t *gdst = a.out + v0 * W;
+            const uint32_t head = (uint32_t)((16 - ((uintptr_t)gdst & 15)) & 15);
+            const uint32_t nbytes = nvt * W;
+            const uint32_t hb = head < nbytes ? head : nbytes;
+            for (uint32_t b = tid * W; b < hb; b += kThreads * W) *(V *)(gdst + b) = *(const V *)(sb + b);
+            const uint32_t body = (nbytes - hb) >> 4;
+            if ((hb & 3) == 0) {
+                for (uint32_t c = tid; c < body; c += kThreads) {
+                    const uint32_t *s32 = (const uint32_t *)(sb + hb + (c << 4));
+                    *(uint4 *)(gdst + hb + (c << 4)) = make_uint4(s32[0], s32[1], s32[2], s32[3]);
+                }
+            } else {
+                for (uint32_t b = hb + tid * W; b < hb + (body << 4); b += kThreads * W)
+                    *(V *)(gdst + b) = *(const V *)(sb + b);
+            }
+            for (uint32_t b = hb + (body << 4) + tid * W; b < nbytes; b += kThreads * W)
+                *(V *)(gdst + b) = *(const V *)(sb + b);
+        }
+        __syncthreads();
+    }
+}
+
+// One kernel per element width (the stream's width is only known on the device): each
+// returns at once unless the header carries its width, so only one does the work.
+template <int W>
+__global__ __launch_bounds__(kThreads) void decompress_kernel(DecompressArgs a) {
+    __shared__ DecShared S;
+    Layout lo;
+    uint64_t pw;
+    int fixed;
+    const bool ok = read_layout(a, lo, pw, fixed);
+    if (W == 1 && !ok) {  // reported once, by the width-1 kernel
+        if (blockIdx.x == 0 && threadIdx.x == 0) set_status(a.status, PCOMP_ECORRUPT);
+        return;
+    }
+    if (!ok || lo.w != W) return;
+    if ((uint64_t)lo.L * lo.w > kTileBytes) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) set_status(a.status, PCOMP_EINVAL);
+        return;
+    }
+    if (lo.n > a.out_cap) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) set_status(a.status, PCOMP_ENOSPC);
+        return;
+    }
+    fill_size_ctx(a.T, lo.L, S.C);
+    __syncthreads();
+    decompress_tiles<W>(a, lo, pw, fixed, S);
+}
+
+__global__ void set_i32_kernel(int32_t *p, int32_t v) { *p = v; }
+
+int launch_decompress(const void *d_in, size_t in_size, void *d_out, size_t out_capacity, int32_t *d_status,
+                      hipStream_t st) {
+    DecompressArgs a;
+    if (tables_for_current_device(&a.T) != PCOMP_OK) return PCOMP_EHIP;
+    set_i32_kernel<<<1, 1, 0, st>>>(d_status, PCOMP_OK);
+    a.in = (const uint8_t *)d_in;
+    a.in_size = in_size;
+    a.out = (uint8_t *)d_out;
+    a.out_cap = out_capacity;
+    a.status = d_status;
+    // persistent grid: enough workgroups to fill every CU several times over
+    const uint64_t max_tiles = in_size > kHdrBytes ? (in_size - kHdrBytes) / 8 : 1;
+    const uint32_t grid = (uint32_t)(max_tiles < 1 ? 1 : (max_tiles < 4096 ? max_tiles : 4096));
+    decompress_kernel<1><<<grid, kThreads, 0, st>>>(a);
+    decompress_kernel<2><<<grid, kThreads, 0, st>>>(a);
+    decompress_kernel<4><<<grid, kThreads, 0, st>>>(a);
+    return hipGetLastError() == hipSuccess ? PCOMP_OK : PCOMP_EHIP;
+}
+
+}  // namespace pcomp

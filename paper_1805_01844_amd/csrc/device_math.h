@@ -37,6 +37,8 @@ __device__ inline Magic magic_dev(uint64_t d) {
     return mg;
 }
 
+__device__ __forceinline__ Magic magic_dev_outline(uint64_t d) { return magic_dev(d); }
+
 __device__ __forceinline__ uint32_t bitlen64(uint64_t x) { return x ? 64 - __clzll(x) : 0; }
 __device__ __forceinline__ uint32_t bitlen32(uint32_t x) { return x ? 32 - __clz(x) : 0; }
 
@@ -102,7 +104,7 @@ __device__ __forceinline__ void slow_word(const SlowBase &sb, uint64_t s, uint32
 }
 
 // Word count of the series (Sec. 3.2) for n digits: walk it word by word.
-__device__ inline uint32_t adv_words_slow(const SlowBase &sb, uint32_t n) {
+__device__ __forceinline__ uint32_t adv_words_slow(const SlowBase sb, uint32_t n) {
     uint64_t s = 1;
     uint32_t q = 0, m = 0;
     for (;;) {
@@ -116,31 +118,37 @@ __device__ inline uint32_t adv_words_slow(const SlowBase &sb, uint32_t n) {
     }
 }
 
-// Word count of the series from the cycle form: c_t = q_t + p_t grows with t, and
-// c_{t + lam} = c_t + V for t >= mu; the count is 1 + the first t with c_t >= n.
-__device__ inline uint32_t adv_words_atlas(const DevTables &T, const BaseDesc &D, uint32_t n) {
-    if (n <= D.k) return 1;  // the first word holds k digits (s_0 = 1)
-    const AtlasEntry *E = T.ent + D.off;
-    uint32_t tot = D.mu + D.lam;
-    uint32_t clast = E[tot - 1].q + E[tot - 1].p;
-    uint32_t lo, hi, j = 0, target = n;
-    if (n <= clast) {
-        lo = 0;
-        hi = tot - 1;
-    } else {
-        j = (n - clast + D.V - 1) / D.V;
-        target = n - j * D.V;
-        lo = D.mu;
-        hi = tot - 1;
-    }
+// c_t = q_t + p_t (values reached by word t, 0-based) from the cycle form: entries
+// 0 .. mu+lam-1 are stored, and c_{t + lam} = c_t + V for t >= mu.
+__host__ __device__ __forceinline__ uint32_t adv_reach(const AtlasEntry *E, const BaseDesc &D, uint32_t t) {
+    const uint32_t tot = D.mu + D.lam;
+    if (t < tot) return E[t].q + E[t].p;
+    const uint32_t c = (t - D.mu) / D.lam;
+    const uint32_t r = t - c * D.lam;
+    return E[r].q + E[r].p + c * D.V;
+}
+
+// Word count of the series for n digits: 1 + the first t with c_t >= n. Every word takes
+// k or k + 1 values (p_t is k - 1 or k, plus the split value) and the first takes k,
+// so (t+1) k <= c_t <= (t+1)(k+1) - 1: the answer lies in
+// [ceil((n+1)/(k+1)) - 1, ceil(n/k) - 1], a range of about n / k^2 words.
+__host__ __device__ inline uint32_t adv_words_cycle(const AtlasEntry *E, const BaseDesc &D, uint32_t n) {
+    const uint32_t k = D.k;
+    if (n <= k) return 1;
+    uint32_t lo = (n + 1 + k) / (k + 1) - 1;  // ceil((n+1)/(k+1)) - 1
+    uint32_t hi = (n + k - 1) / k - 1;        // ceil(n/k) - 1
     while (lo < hi) {
-        uint32_t mid = (lo + hi) >> 1;
-        if (E[mid].q + E[mid].p >= target)
+        const uint32_t mid = (lo + hi) >> 1;
+        if (adv_reach(E, D, mid) >= n)
             hi = mid;
         else
             lo = mid + 1;
     }
-    return lo + j * D.lam + 1;
+    return lo + 1;
+}
+
+__device__ __forceinline__ uint32_t adv_words_atlas(const DevTables &T, const BaseDesc &D, uint32_t n) {
+    return adv_words_cycle(T.ent + D.off, D, n);
 }
 
 // Entry and q_i of word i from the cycle form.

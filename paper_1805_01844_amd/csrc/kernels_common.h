@@ -1,0 +1,292 @@
+// kernels_common.h -- pieces shared by the compress and decompress kernels (device code).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "device_math.h"
+#include "pcomp_internal.h"
+
+namespace pcomp {
+
+template <int W>
+struct Elem;
+template <>
+struct Elem<1> {
+    typedef uint8_t T;
+};
+template <>
+struct Elem<2> {
+    typedef uint16_t T;
+};
+template <>
+struct Elem<4> {
+    typedef uint32_t T;
+};
+
+// ---------------------------------------------------------------------------------------
+// Group collectives: G lanes (a power of two, aligned) cooperate on one block. Within a
+// wavefront they use cross-lane shuffles; groups wider than a wavefront combine per-wave
+// partials through LDS. Every thread of the workgroup must call these (they may hold
+// barriers when G > 64).
+// ---------------------------------------------------------------------------------------
+template <typename T, typename Op>
+__device__ __forceinline__ T group_reduce(T x, uint32_t G, Op op, T *scratch) {
+    const uint32_t width = G < 64 ? G : 64;
+    for (uint32_t o = 1; o < width; o <<= 1) x = op(x, __shfl_xor(x, o, 64));
+    if (G > 64) {
+        const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        __syncthreads();
+        if (lane == 0) scratch[wave] = x;
+        __syncthreads();
+        const uint32_t wpg = G >> 6, w0 = (wave / wpg) * wpg;
+        T r = scratch[w0];
+        for (uint32_t i = 1; i < wpg; i++) r = op(r, scratch[w0 + i]);
+        x = r;
+        __syncthreads();
+    }
+    return x;
+}
+
+// Exclusive prefix sum over the G lanes of a group, in lane order.
+__device__ __forceinline__ uint32_t group_excl_scan(uint32_t x, uint32_t G, uint32_t *scratch) {
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t width = G < 64 ? G : 64;
+    const uint32_t gl = lane & (width - 1);
+    uint32_t inc = x;
+    for (uint32_t o = 1; o < width; o <<= 1) {
+        const uint32_t y = __shfl_up(inc, o, width);
+        if (gl >= o) inc += y;
+    }
+    uint32_t excl = inc - x;
+    if (G > 64) {
+        const uint32_t wave = threadIdx.x >> 6;
+        __syncthreads();
+        if (lane == 63) scratch[wave] = inc;
+        __syncthreads();
+        const uint32_t wpg = G >> 6, w0 = (wave / wpg) * wpg;
+        for (uint32_t i = w0; i < wave; i++) excl += scratch[i];
+        __syncthreads();
+    }
+    return excl;
+}
+
+// Exclusive prefix sum of x over the workgroup (thread order); *total gets the sum.
+__device__ __forceinline__ uint32_t wg_excl_scan(uint32_t x, uint32_t *scratch, uint32_t *total) {
+    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t inc = x;
+    for (uint32_t o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += y;
+    }
+    if (lane == 63) scratch[wave] = inc;
+    __syncthreads();
+    uint32_t add = 0, tot = 0;
+    for (uint32_t w = 0; w < kThreads / 64; w++) {
+        const uint32_t v = scratch[w];
+        add += w < wave ? v : 0;
+        tot += v;
+    }
+    __syncthreads();
+    *total = tot;
+    return inc - x + add;
+}
+
+struct MinOp {
+    __device__ uint32_t operator()(uint32_t a, uint32_t b) const { return a < b ? a : b; }
+    __device__ uint64_t operator()(uint64_t a, uint64_t b) const { return a < b ? a : b; }
+};
+struct MaxOp {
+    __device__ uint32_t operator()(uint32_t a, uint32_t b) const { return a > b ? a : b; }
+};
+struct AddOp {
+    __device__ uint64_t operator()(uint64_t a, uint64_t b) const { return a + b; }
+};
+
+// ---------------------------------------------------------------------------------------
+// Word counts with per-workgroup caches in LDS: the largest base for k digits per word,
+// and, for the main part of threshold classes (base 2^j + 1), k and the advanced word
+// count of a full block.
+// ---------------------------------------------------------------------------------------
+struct SizeCtx {
+    uint64_t kmax[65];
+    uint32_t p1_k[32];
+    uint32_t p1_adv[32];
+};
+
+__device__ inline void fill_size_ctx(const DevTables &T, uint32_t L, SizeCtx &C) {
+    const uint32_t t = threadIdx.x;
+    if (t < 65) C.kmax[t] = T.kmax[t];
+    if (t >= 96 && t < 128) {
+        const uint32_t j = t - 96;
+        const BaseDesc &D = T.desc[atlas_index((1ull << j) + 1)];
+        C.p1_k[j] = D.k;
+        C.p1_adv[j] = adv_words_atlas(T, D, L);
+    }
+}
+
+// k(B) = max{k : B^k <= 2^64} for B >= 2 (Sec. 3.1 Eq. (1), exact reading), from a float
+// estimate corrected against the exact table.
+__device__ __forceinline__ uint32_t k_fast(const SizeCtx &C, uint64_t B) {
+    uint32_t k = (uint32_t)(64.0f / __log2f((float)B));
+    k = k < 1 ? 1 : (k > 64 ? 64 : k);
+    while (k < 64 && B <= C.kmax[k + 1]) k++;
+    while (B > C.kmax[k]) k--;
+    return k;
+}
+
+// Words of family fam (0 basic Sec. 3.1, 1 advanced Sec. 3.2) for n digits of `base`;
+// `full` is the block length L (a block of n == L values can use the cache).
+__device__ inline uint32_t fam_words(const DevTables &T, const SizeCtx &C, int fam, uint32_t n, uint64_t base,
+                                     uint32_t full) {
+    if (n == 0 || base <= 1) return 0;
+    const uint32_t k = k_fast(C, base);
+    if (!fam) return (n + k - 1) / k;
+    if (n <= k) return 1;
+    const uint64_t bm1 = base - 1;
+    if ((bm1 & (bm1 - 1)) == 0 && n == full) return C.p1_adv[bitlen64(bm1) - 1];  // base 2^j + 1
+    const int ai = atlas_index(base);
+    if (ai >= 0) return adv_words_atlas(T, T.desc[ai], n);
+    return adv_words_slow(slow_base(T, base), n);
+}
+
+// Words of class c = 8 family + t for a block of Lb digits of base B (beta = bitlen(B-1));
+// ne_t = digits >= T = 2^(beta - t). nw_main receives the main-part words.
+__device__ inline uint32_t class_words(const DevTables &T, const SizeCtx &C, uint32_t L, int c, uint32_t Lb,
+                                       uint64_t B, uint32_t beta, uint32_t ne_t, uint32_t &nw_main) {
+    const int fam = c >> 3, t = c & 7;
+    if (t == 0) {
+        nw_main = fam_words(T, C, fam, Lb, B, L);
+        return nw_main;
+    }
+    const uint32_t j = beta - t;
+    const uint64_t Th = 1ull << j;
+    if (!fam)
+        nw_main = (Lb + C.p1_k[j] - 1) / C.p1_k[j];
+    else
+        nw_main = (Lb == L) ? C.p1_adv[j] : fam_words(T, C, 1, Lb, Th + 1, L);
+    return nw_main + fam_words(T, C, fam, ne_t, B - Th, L);
+}
+
+// ---------------------------------------------------------------------------------------
+// Digit arithmetic in 32-bit chunks (see Chunk).
+// ---------------------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t div32_magic(uint32_t x, uint32_t m, uint32_t sh) {
+    const uint32_t t = __umulhi(m, x);
+    return (t + ((x - t) >> 1)) >> sh;
+}
+
+// Resolved constants of one base for packing / unpacking a part of a block.
+struct PartBase {
+    uint64_t base;
+    uint32_t k;           // digits per basic word
+    Chunk ch;             // 32-bit chunking (h = 0: digit by digit in 64 bits)
+    Magic mB;             // 64-bit division by the base (h = 0 path, and advanced split values)
+    const BaseDesc *D;    // schedule of the advanced series, nullptr outside the tables
+};
+
+__device__ __forceinline__ PartBase resolve_base(const DevTables &T, const SizeCtx &C, uint64_t base) {
+    PartBase pb;
+    pb.base = base;
+    const int ai = atlas_index(base);
+    if (ai >= 0) {
+        const BaseDesc &D = T.desc[ai];
+        pb.k = D.k;
+        pb.ch = D.ch;
+        pb.mB = D.mB;
+        pb.D = &D;
+    } else {
+        pb.k = k_fast(C, base);
+        pb.ch.h = 0;
+        pb.mB = magic_dev_outline(base);
+        pb.D = nullptr;
+    }
+    return pb;
+}
+
+// Horner over a digit sequence, first digit at the highest power: `lead` then
+// get(j0) .. get(j0 + cnt - 1). Chunks of h digits use 24-bit multiply-adds; the chunks
+// are joined by one 64-bit multiply-add each (the first chunk holds total mod h digits).
+template <typename Get>
+__device__ __forceinline__ uint64_t horner_digits(const PartBase &pb, uint32_t lead, uint32_t j0, uint32_t cnt,
+                                                  Get get) {
+    if (pb.ch.h == 0) {
+        uint64_t acc = lead;
+        for (uint32_t j = 0; j < cnt; j++) acc = acc * pb.base + get(j0 + j);
+        return acc;
+    }
+    const uint32_t B = (uint32_t)pb.base, h = pb.ch.h;
+    const uint32_t total = cnt + 1;
+    uint32_t first = total % h;
+    if (first == 0) first = h;
+    uint32_t s = lead, j = j0;
+    for (uint32_t m = 1; m < first; m++) s = __umul24(s, B) + (uint32_t)get(j++);
+    uint64_t acc = s;
+    for (uint32_t c = first; c < total; c += h) {
+        s = 0;
+        for (uint32_t m = 0; m < h; m++) s = __umul24(s, B) + (uint32_t)get(j++);
+        acc = acc * pb.ch.P + s;
+    }
+    return acc;
+}
+
+// Peels the lowest cnt base-B digits off X: put(j0 + cnt - 1, lowest digit), ...,
+// put(j0, highest of them); returns what remains above them.
+template <typename Put>
+__device__ __forceinline__ uint64_t peel_digits(const PartBase &pb, uint64_t X, uint32_t j0, uint32_t cnt, Put put) {
+    if (pb.ch.h == 0) {
+        for (int j = (int)cnt - 1; j >= 0; j--) {
+            const uint64_t q = div_magic(X, pb.mB);
+            put(j0 + j, (uint32_t)(X - q * pb.base));
+            X = q;
+        }
+        return X;
+    }
+    const uint32_t B = (uint32_t)pb.base, h = pb.ch.h;
+    uint32_t j = j0 + cnt;
+    uint32_t rem = cnt;
+    while (rem >= h) {
+        const uint64_t q = div_magic(X, pb.ch.mP);
+        uint32_t x = (uint32_t)(X - q * pb.ch.P);
+        X = q;
+        for (uint32_t m = 0; m < h; m++) {
+            const uint32_t qq = div32_magic(x, pb.ch.m32, pb.ch.sh32);
+            put(--j, x - __umul24(qq, B));
+            x = qq;
+        }
+        rem -= h;
+    }
+    if (rem) {
+        uint32_t x = (uint32_t)X;  // fewer than h digits (plus a top digit) remain: X < B^h < 2^32
+        for (uint32_t m = 0; m < rem; m++) {
+            const uint32_t qq = div32_magic(x, pb.ch.m32, pb.ch.sh32);
+            put(--j, x - __umul24(qq, B));
+            x = qq;
+        }
+        X = x;
+    }
+    return X;
+}
+
+__device__ __forceinline__ void put_le(uint8_t *p, uint64_t v, int bytes) {
+    if (bytes == 1) {
+        *p = (uint8_t)v;
+    } else if (bytes == 2 && !((uintptr_t)p & 1)) {
+        *(uint16_t *)p = (uint16_t)v;
+    } else if (bytes == 4 && !((uintptr_t)p & 3)) {
+        *(uint32_t *)p = (uint32_t)v;
+    } else if (bytes == 8 && !((uintptr_t)p & 7)) {
+        *(uint64_t *)p = v;
+    } else {
+        for (int i = 0; i < bytes; i++) p[i] = (uint8_t)(v >> (8 * i));
+    }
+}
+
+__device__ __forceinline__ uint64_t get_le(const uint8_t *p, int bytes) {
+    if (bytes == 1) return *p;
+    if (bytes == 2 && !((uintptr_t)p & 1)) return *(const uint16_t *)p;
+    if (bytes == 4 && !((uintptr_t)p & 3)) return *(const uint32_t *)p;
+    uint64_t v = 0;
+    for (int i = 0; i < bytes; i++) v |= (uint64_t)p[i] << (8 * i);
+    return v;
+}
+
+}  // namespace pcomp

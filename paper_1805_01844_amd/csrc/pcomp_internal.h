@@ -13,6 +13,7 @@ constexpr uint32_t kHdrBytes = 64;
 constexpr uint32_t kTileBytes = 16384;  // format constant: tile_blocks * L * w <= kTileBytes
 constexpr uint32_t kMaxTileBlocks = 256;
 constexpr uint32_t kThreads = 256;  // threads per workgroup of every kernel
+constexpr uint32_t kCtxBytes = 1024;  // workspace slot of the per-launch size tables
 
 constexpr unsigned kFlagClass = 1, kFlagNe = 2, kFlagNe16 = 4;
 
@@ -34,11 +35,24 @@ struct Magic {
 // (s_0 = 1) every word i uses p_i = k if s_i <= Qk else k - 1, R_i = floor(Q_{p_i} / s_i),
 // and the next state is ceil(B / R_i). The state sequence is eventually periodic:
 // s_{i + lam} = s_i for i >= mu, so entries 0 .. mu+lam-1 describe every word.
+// Digits handled in 32-bit chunks: h digits per chunk with P = B^h < 2^32 and B^(h-1) < 2^24,
+// so a chunk is built by 24-bit multiply-adds and split from a word by one 64-bit magic
+// division by P; inside a chunk the digits come out by 32-bit magic division by B.
+// h = 0 when B >= 2^24 (digits then go one by one through 64-bit arithmetic).
+struct Chunk {
+    Magic mP;      // 64-bit division by P
+    uint32_t h;    // digits per chunk
+    uint32_t P;    // B^h
+    uint32_t m32;  // 32-bit magic for B: q = (t + ((x - t) >> 1)) >> sh32, t = mulhi32(m32, x)
+    uint32_t sh32;
+};
+
 struct BaseDesc {
     uint64_t Qk;   // floor(2^64 / B^k)
     uint64_t Qk1;  // floor(2^64 / B^(k-1))
     Magic mB;      // division by B
     Magic mBp[2];  // division by B^(k-1) and by B^k (the latter unused when B^k = 2^64)
+    Chunk ch;      // 32-bit chunking of digits
     uint32_t off;  // first AtlasEntry
     uint32_t V;    // values consumed by one cycle: q_{mu+lam} - q_mu
     uint16_t mu, lam;

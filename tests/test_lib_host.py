@@ -78,3 +78,19 @@ def test_schedule_cycles_are_short(pc):
         worst = max(worst, mu + lam)
         assert lam >= 1 and V > 0
     assert worst < 600
+
+
+def test_cycle_form_word_counts_match_oracle(pc, orc):
+    # the bounded search over the cycle form gives the oracle's word count of the series
+    import ctypes
+    L = pc.lib()
+    L.pcomp_atlas_words.restype = ctypes.c_int
+    L.pcomp_atlas_words.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_void_p]
+    rng = np.random.default_rng(3)
+    bases = list(range(2, 200)) + [int(b) for b in rng.integers(200, 65538, 200)] + [65536, 65537]
+    bases += [(1 << j) + 1 for j in range(17, 32)]
+    out = ctypes.c_uint32()
+    for B in bases:
+        for n in [1, 2, 5, 13, 14, 40, 41, 154, 1000, 1024, 4096, 65535]:
+            assert L.pcomp_atlas_words(B, n, ctypes.byref(out)) == 0
+            assert out.value == orc.adv_words(n, B), (B, n)
