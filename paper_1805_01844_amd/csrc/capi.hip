@@ -15,8 +15,12 @@ namespace {
 bool dtype_ok(int w) { return w == 1 || w == 2 || w == 4; }
 bool variant_ok(int v) { return (v >= 0 && v < 16) || v == PCOMP_SELECT_EXHAUSTIVE || v == PCOMP_SELECT_LEARNED; }
 
-// Workspace: [err u32, 0 u32][size tables, kCtxBytes][one u32 word total per tile].
-size_t ws_bytes_for(const Layout &lo) { return 8 + kCtxBytes + 4 * (size_t)(lo.n_tiles ? lo.n_tiles : 1); }
+// Workspace: [err u32, 0 u32][size tables, kCtxBytes][one u32 word total per tile, padded to
+// 8 bytes][one u64 sum per run of 8192 tiles].
+size_t ws_bytes_for(const Layout &lo) {
+    const size_t nt = lo.n_tiles ? lo.n_tiles : 1;
+    return 8 + kCtxBytes + 4 * ((nt + 1) & ~(size_t)1) + 8 * ((nt + 8191) / 8192);
+}
 
 }  // namespace
 

@@ -250,32 +250,54 @@ __global__ __launch_bounds__(kThreads) void stats_kernel(CompressArgs a) {
 }
 
 // ---- launch 2: tile index (exclusive prefix of the tile totals) and header --------------
-constexpr uint32_t kScanThreads = 1024;
+// Two small launches: every workgroup sums a run of kScanTiles tile totals; then every
+// workgroup adds the sums of the runs before its own and scans its run into the index.
+constexpr uint32_t kScanPer = 32;                      // tile totals per thread
+constexpr uint32_t kScanTiles = kScanPer * kThreads;  // tile totals per workgroup
 
-__global__ __launch_bounds__(kScanThreads) void scan_kernel(CompressArgs a) {
-    __shared__ uint64_t s_part[kScanThreads];
+__global__ __launch_bounds__(kThreads) void scan_sums_kernel(CompressArgs a, uint64_t *sums) {
+    __shared__ uint32_t s_red32[kThreads / 64];
+    const uint64_t nt = a.lo.n_tiles;
+    const uint64_t t0 = (uint64_t)blockIdx.x * kScanTiles;
+    uint32_t sum = 0;
+    for (uint32_t m = 0; m < kScanPer; m++) {
+        const uint64_t t = t0 + (uint64_t)m * kThreads + threadIdx.x;  // coalesced
+        if (t < nt) sum += a.tile_words[t];
+    }
+    uint32_t total;
+    wg_excl_scan(sum, s_red32, &total);
+    if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(kThreads) void scan_index_kernel(CompressArgs a, const uint64_t *sums) {
+    __shared__ uint32_t s_red32[kThreads / 64];
+    __shared__ uint64_t s_red64[kThreads / 64];
     const Layout &lo = a.lo;
     const uint64_t nt = lo.n_tiles;
     const uint32_t tid = threadIdx.x;
-    const uint64_t per = (nt + kScanThreads - 1) / kScanThreads;
-    const uint64_t t0 = tid * per < nt ? tid * per : nt, t1 = (tid + 1) * per < nt ? (tid + 1) * per : nt;
-    uint64_t sum = 0;
-    for (uint64_t t = t0; t < t1; t++) sum += a.tile_words[t];
-    s_part[tid] = sum;
-    __syncthreads();
-    for (uint32_t o = 1; o < kScanThreads; o <<= 1) {  // inclusive Hillis-Steele scan of the partials
-        const uint64_t y = tid >= o ? s_part[tid - o] : 0;
-        __syncthreads();
-        s_part[tid] += y;
-        __syncthreads();
+    // sum of the runs before this one
+    uint64_t before = 0;
+    for (uint32_t r = tid; r < blockIdx.x; r += kThreads) before += sums[r];
+    before = group_reduce(before, kThreads, AddOp(), s_red64);
+    // this thread's kScanPer consecutive tiles
+    const uint64_t t0 = (uint64_t)blockIdx.x * kScanTiles + (uint64_t)tid * kScanPer;
+    uint32_t v[kScanPer];
+    uint32_t sum = 0;
+#pragma unroll
+    for (uint32_t m = 0; m < kScanPer; m++) {
+        v[m] = (t0 + m < nt) ? a.tile_words[t0 + m] : 0;
+        sum += v[m];
     }
-    uint64_t run = s_part[tid] - sum;
+    uint32_t total;
+    const uint32_t ex = wg_excl_scan(sum, s_red32, &total);
+    uint64_t run = before + ex;
     uint64_t *index = (uint64_t *)(a.out + lo.off_index);
-    for (uint64_t t = t0; t < t1; t++) {
-        index[t] = run;
-        run += a.tile_words[t];
+#pragma unroll
+    for (uint32_t m = 0; m < kScanPer; m++) {
+        if (t0 + m < nt) index[t0 + m] = run;
+        run += v[m];
     }
-    if (tid == kScanThreads - 1) write_header(a, s_part[tid]);
+    if (blockIdx.x == gridDim.x - 1 && tid == 0) write_header(a, before + total);
 }
 
 // ---- launch 3: packing ----------------------------------------------------------------
@@ -391,7 +413,8 @@ __global__ void prep_kernel(uint32_t *err, SizeCtx *ctx, DevTables T, uint32_t L
     if (threadIdx.x == 0) *err = 0;
 }
 
-// Workspace: [err u32, 0 u32][SizeCtx padded to kCtxBytes][one u32 word total per tile].
+// Workspace: [err u32, 0 u32][SizeCtx padded to kCtxBytes][one u32 word total per tile, padded
+// to 8 bytes][one u64 sum per run of kScanTiles tiles].
 int launch_compress(const void *d_in, const Layout &lo, int variant, void *d_out, uint64_t *d_out_size,
                     uint64_t *ws, uint64_t ws_words, hipStream_t st) {
     CompressArgs a;
@@ -417,7 +440,10 @@ int launch_compress(const void *d_in, const Layout &lo, int variant, void *d_out
         else
             stats_kernel<4><<<grid, kThreads, 0, st>>>(a);
     }
-    scan_kernel<<<1, kScanThreads, 0, st>>>(a);
+    const uint32_t runs = (uint32_t)((lo.n_tiles + kScanTiles - 1) / kScanTiles);
+    uint64_t *sums = (uint64_t *)(wsb + 8 + kCtxBytes + 4 * ((lo.n_tiles + 1) & ~1ull));
+    if (runs > 0) scan_sums_kernel<<<runs, kThreads, 0, st>>>(a, sums);
+    scan_index_kernel<<<runs > 0 ? runs : 1, kThreads, 0, st>>>(a, sums);
     if (lo.n_tiles) {
         if (lo.w == 1)
             pack_kernel<1><<<grid, kThreads, dyn, st>>>(a);
