@@ -95,8 +95,9 @@ int pcomp_init(void);
  * Returns 0 for invalid arguments. */
 size_t pcomp_bound(uint64_t n, pcomp_dtype dtype, uint32_t block_len, int variant);
 
-/* Host-only, pure. Device workspace bytes that pcomp_compress needs (tile
- * look-back descriptors and a ticket counter). Returns 0 for invalid args. */
+/* Host-only, pure. Device workspace bytes that pcomp_compress needs (an error
+ * word, size tables, per-tile word totals and their prefix sums). Returns 0
+ * for invalid args. */
 size_t pcomp_workspace_size(uint64_t n, pcomp_dtype dtype, uint32_t block_len, int variant);
 
 /* Compresses n values of `dtype` at d_in (any alignment of the element type)
@@ -121,6 +122,63 @@ int pcomp_decompress(const void *d_in, size_t in_size, void *d_out, size_t out_c
  * PCOMP_ECORRUPT. */
 int pcomp_stream_info(const void *h_header, uint64_t *n, int *dtype_bytes, uint32_t *block_len,
                       uint64_t *total_bytes);
+
+/* ---- Batches ----------------------------------------------------------------
+ * Many independent arrays ("segments": camera events of any shape and dtype)
+ * compressed by one fixed sequence of launches, so a HIP graph can capture a
+ * whole batch. Blocks never cross segments (the method blocks each array on its
+ * own, Sec. 3.3); every segment becomes its own v1 stream, exactly the stream
+ * pcomp_compress would write for it alone with the same block length and
+ * variant. Streams sit in the batch buffer in the caller's order, each in a
+ * slot of its pcomp_bound, at offsets the plan fixes.
+ *
+ * A plan is built on the host from the segment list and must then be copied,
+ * byte for byte, to device memory by the caller (8-byte aligned); calls take
+ * both copies (sizes and launch shapes come from the host copy, the kernels
+ * read the device copy). A plan records the segment pointers: for compression
+ * they are the inputs; for decompression build a plan of the same segments
+ * (same order, sizes, dtypes, block lengths, variant) whose pointers are the
+ * destinations. */
+typedef struct {
+    const void *ptr; /* device pointer to the segment's values (aligned to its dtype) */
+    uint64_t n;      /* values */
+    uint32_t dtype;  /* pcomp_dtype */
+    uint32_t reserved;
+} pcomp_segment;
+
+/* Host-only. Plan bytes for this batch; block_len[3] gives the block length of
+ * the u8, u16 and u32 segments (each with block_len * dtype bytes <= 16384
+ * where such segments exist). Returns 0 for invalid arguments. */
+size_t pcomp_batch_plan_bytes(const pcomp_segment *h_segs, uint32_t n_segs, const uint32_t *block_len,
+                              int variant);
+
+/* Host-only. Writes the plan (8-byte aligned host buffer of plan_bytes).
+ * Returns PCOMP_OK, PCOMP_EINVAL, PCOMP_ENOSPC (buffer too small) or
+ * PCOMP_ENOMODEL. */
+int pcomp_batch_plan(const pcomp_segment *h_segs, uint32_t n_segs, const uint32_t *block_len, int variant,
+                     void *h_plan, size_t plan_bytes);
+
+/* Host-only. From a host plan: batch buffer bytes, workspace bytes, tile
+ * count, and (if h_offsets is not NULL) the byte offset of every segment's
+ * stream, in the caller's order (n_segs entries). */
+int pcomp_batch_info(const void *h_plan, uint64_t *out_bytes, uint64_t *ws_bytes, uint64_t *n_tiles,
+                     uint64_t *h_offsets);
+
+/* Compresses every segment of the plan into d_out (out_capacity >= the plan's
+ * buffer bytes); the stream size of segment i goes to d_sizes[i] (device u64).
+ * grid = 0 runs the per-tile launches with one workgroup per tile; grid > 0
+ * makes them persistent with that many workgroups per width group. The
+ * workspace rules of pcomp_compress apply. */
+int pcomp_compress_batch(const void *h_plan, const void *d_plan, void *d_out, size_t out_capacity,
+                         uint64_t *d_sizes, void *d_ws, size_t ws_bytes, uint32_t grid, void *stream);
+
+/* Decompresses the streams of a batch buffer (in_size bytes at d_in, streams
+ * at the plan's offsets) into the plan's segment pointers. *d_status gets
+ * PCOMP_OK or PCOMP_ECORRUPT (a header disagrees with the plan, or a stream is
+ * inconsistent). grid = 0 picks min(tiles, 4096) workgroups per width group.
+ * No workspace is needed. */
+int pcomp_decompress_batch(const void *h_plan, const void *d_plan, const void *d_in, size_t in_size,
+                           int32_t *d_status, uint32_t grid, void *stream);
 
 #ifdef __cplusplus
 }

@@ -57,6 +57,16 @@ def lib():
         L.pcomp_atlas_info.argtypes = [u64, vp, vp, vp, vp]
         L.pcomp_atlas_word.restype = i32
         L.pcomp_atlas_word.argtypes = [u64, u32, vp, vp, vp, vp]
+        L.pcomp_batch_plan_bytes.restype = sz
+        L.pcomp_batch_plan_bytes.argtypes = [vp, u32, vp, i32]
+        L.pcomp_batch_plan.restype = i32
+        L.pcomp_batch_plan.argtypes = [vp, u32, vp, i32, vp, sz]
+        L.pcomp_batch_info.restype = i32
+        L.pcomp_batch_info.argtypes = [vp, vp, vp, vp, vp]
+        L.pcomp_compress_batch.restype = i32
+        L.pcomp_compress_batch.argtypes = [vp, vp, vp, sz, vp, vp, sz, u32, vp]
+        L.pcomp_decompress_batch.restype = i32
+        L.pcomp_decompress_batch.argtypes = [vp, vp, vp, sz, vp, u32, vp]
         _lib = L
     return _lib
 
@@ -167,3 +177,126 @@ def atlas_word(B: int, i: int):
     _check(lib().pcomp_atlas_word(B, i, ctypes.byref(s), ctypes.byref(p), ctypes.byref(R), ctypes.byref(q)),
            "pcomp_atlas_word")
     return s.value, p.value, R.value, q.value
+
+
+# ---- batches ---------------------------------------------------------------------------
+
+class _Segment(ctypes.Structure):
+    _fields_ = [("ptr", ctypes.c_void_p), ("n", ctypes.c_uint64), ("dtype", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
+
+
+def _block_lens(block_len):
+    """Block length per width group (u8, u16, u32) from an int or a 3-sequence."""
+    if isinstance(block_len, int):
+        return (block_len, block_len, block_len)
+    bl = tuple(int(x) for x in block_len)
+    assert len(bl) == 3
+    return bl
+
+
+class _Plan:
+    """A batch plan: host copy (ctypes buffer) and device copy (u8 tensor)."""
+
+    def __init__(self, tensors, block_len, variant, device):
+        for t in tensors:
+            assert t.is_cuda and t.is_contiguous() and t.dtype in _DT, "segments are contiguous u8/u16/u32 CUDA tensors"
+        self.n_segs = len(tensors)
+        self.segs = (_Segment * max(1, self.n_segs))()
+        for i, t in enumerate(tensors):
+            self.segs[i] = _Segment(t.data_ptr(), t.numel(), _DT[t.dtype], 0)
+        self.L = (ctypes.c_uint32 * 3)(*_block_lens(block_len))
+        self.variant = int(variant)
+        nb = lib().pcomp_batch_plan_bytes(self.segs, self.n_segs, self.L, self.variant)
+        if nb == 0:
+            raise PcompError(EINVAL, "pcomp_batch_plan_bytes")
+        self.host = (ctypes.c_uint64 * ((nb + 7) // 8))()
+        _check(lib().pcomp_batch_plan(self.segs, self.n_segs, self.L, self.variant, self.host, nb), "pcomp_batch_plan")
+        ob, wb, nt = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+        offs = (ctypes.c_uint64 * max(1, self.n_segs))()
+        _check(lib().pcomp_batch_info(self.host, ctypes.byref(ob), ctypes.byref(wb), ctypes.byref(nt), offs),
+               "pcomp_batch_info")
+        self.out_bytes, self.ws_bytes, self.n_tiles = ob.value, wb.value, nt.value
+        self.offsets = [offs[i] for i in range(self.n_segs)]
+        raw = bytes(memoryview(self.host).cast("B")[:nb])
+        self.device = torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(device)
+
+
+class Batch:
+    """Compression of a list of segments (any mix of u8/u16/u32 CUDA tensors and lengths) by one
+    fixed sequence of launches. Buffers are allocated once; ``compress()`` enqueues the launches
+    on the current stream and allocates nothing, so it can be captured in a HIP graph
+    (``capture()``). Each segment becomes its own stream, identical to ``compress(segment)``.
+    ``grid`` = 0 runs one workgroup per tile; otherwise the per-tile launches are persistent
+    with that many workgroups."""
+
+    def __init__(self, tensors, block_len=1024, variant=0, grid=0, device="cuda"):
+        self.tensors = list(tensors)
+        self.variant, self.grid = int(variant), int(grid)
+        self.block_len = _block_lens(block_len)
+        self.plan = _Plan(self.tensors, self.block_len, self.variant, device)
+        self.out = torch.empty(max(8, self.plan.out_bytes), dtype=torch.uint8, device=device)
+        self.ws = torch.empty(max(8, self.plan.ws_bytes), dtype=torch.uint8, device=device)
+        self.sizes = torch.zeros(max(1, self.plan.n_segs), dtype=torch.int64, device=device)
+        self.graph = None
+
+    @property
+    def offsets(self):
+        return self.plan.offsets
+
+    def compress(self) -> None:
+        rc = lib().pcomp_compress_batch(self.plan.host, ctypes.c_void_p(self.plan.device.data_ptr()),
+                                        ctypes.c_void_p(self.out.data_ptr()), self.out.numel(),
+                                        ctypes.c_void_p(self.sizes.data_ptr()), ctypes.c_void_p(self.ws.data_ptr()),
+                                        self.ws.numel(), self.grid, _stream_handle())
+        _check(rc, "pcomp_compress_batch")
+
+    def capture(self):
+        """Captures compress() in a CUDA/HIP graph (after one eager warm-up call); returns the graph,
+        whose replay() re-runs the whole batch."""
+        self.compress()
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.compress()
+        self.graph = g
+        return g
+
+    def error_flag(self) -> int:
+        return int(self.ws[:4].view(torch.int32).item())
+
+    def total_bytes(self) -> int:
+        return int(self.sizes[:self.plan.n_segs].sum().item())
+
+    def streams(self):
+        """Views of every segment's stream (synchronises)."""
+        err = self.error_flag()
+        if err:
+            raise PcompError(EHIP, "pcomp_compress_batch (device error word %d)" % err)
+        sz = self.sizes[:self.plan.n_segs].tolist()
+        return [self.out[o:o + s] for o, s in zip(self.plan.offsets, sz)]
+
+
+class BatchDecoder:
+    """Decompression of a Batch's buffer into destination tensors shaped like its segments."""
+
+    def __init__(self, batch: Batch, outs, grid=0):
+        assert len(outs) == len(batch.tensors)
+        for t, o in zip(batch.tensors, outs):
+            assert o.numel() == t.numel() and o.dtype == t.dtype
+        self.batch, self.outs, self.grid = batch, list(outs), int(grid)
+        self.plan = _Plan(self.outs, batch.block_len, batch.variant, batch.out.device)
+        assert self.plan.offsets == batch.plan.offsets
+        self.status = torch.zeros(1, dtype=torch.int32, device=batch.out.device)
+
+    def __call__(self, buf: torch.Tensor = None) -> None:
+        buf = self.batch.out if buf is None else buf
+        rc = lib().pcomp_decompress_batch(self.plan.host, ctypes.c_void_p(self.plan.device.data_ptr()),
+                                          ctypes.c_void_p(buf.data_ptr()), buf.numel(),
+                                          ctypes.c_void_p(self.status.data_ptr()), self.grid, _stream_handle())
+        _check(rc, "pcomp_decompress_batch")
+
+    def check(self) -> None:
+        st = int(self.status.item())
+        if st != OK:
+            raise PcompError(st, "pcomp_decompress_batch (device status)")

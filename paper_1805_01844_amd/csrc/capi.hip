@@ -1,11 +1,19 @@
 // capi.hip -- the C ABI declared in include/pcomp.h: argument checks, sizes, launches.
+#include <vector>
+
 #include "pcomp_internal.h"
 
 namespace pcomp {
-int launch_compress(const void *d_in, const Layout &lo, int variant, void *d_out, uint64_t *d_out_size,
-                    uint64_t *ws, uint64_t ws_words, hipStream_t st);
+uint64_t compress_ws_bytes(uint64_t n_tiles);
+int launch_compress(const void *d_in, const Layout &lo, int variant, void *d_out, uint64_t *d_out_size, void *ws,
+                    hipStream_t st);
+int launch_compress_table(const SegDesc *segs, const uint32_t *tile_seg, const SegDesc &one, uint32_t n_segs,
+                          const uint64_t *tile_lo, const uint64_t *tile_hi, const uint32_t *L, uint64_t n_tiles,
+                          int variant, void *d_out, uint64_t *d_sizes, void *ws, uint32_t grid, hipStream_t st);
 int launch_decompress(const void *d_in, size_t in_size, void *d_out, size_t out_capacity, int32_t *d_status,
                       hipStream_t st);
+int launch_decompress_batch(const BatchPlanHeader &ph, const SegDesc *d_segs, const uint32_t *d_tile_seg,
+                            const void *d_in, size_t in_size, int32_t *d_status, uint32_t grid, hipStream_t st);
 }  // namespace pcomp
 
 using namespace pcomp;
@@ -15,11 +23,46 @@ namespace {
 bool dtype_ok(int w) { return w == 1 || w == 2 || w == 4; }
 bool variant_ok(int v) { return (v >= 0 && v < 16) || v == PCOMP_SELECT_EXHAUSTIVE || v == PCOMP_SELECT_LEARNED; }
 
-// Workspace: [err u32, 0 u32][size tables, kCtxBytes][one u32 word total per tile, padded to
-// 8 bytes][one u64 sum per run of 8192 tiles].
-size_t ws_bytes_for(const Layout &lo) {
-    const size_t nt = lo.n_tiles ? lo.n_tiles : 1;
-    return 8 + kCtxBytes + 4 * ((nt + 1) & ~(size_t)1) + 8 * ((nt + 8191) / 8192);
+size_t ws_bytes_for(const Layout &lo) { return (size_t)compress_ws_bytes(lo.n_tiles); }
+
+// Bound of one stream: every block at most its basic t = 0 size (see pcomp_bound).
+uint64_t bound_of(const Layout &lo) {
+    const uint64_t per = 8 / lo.w;  // digits per word of a full-range block: 64 / (8 w)
+    uint64_t words = 0;
+    if (lo.n_blocks) {
+        const uint64_t last = lo.n - (lo.n_blocks - 1) * lo.L;
+        words = (lo.n_blocks - 1) * ((lo.L + per - 1) / per) + (last + per - 1) / per;
+    }
+    return lo.off_payload + 8 * words;
+}
+
+int group_of(int w) { return w == 1 ? 0 : w == 2 ? 1 : 2; }
+
+// Checks a batch and returns its tile count and plan size.
+int batch_shape(const pcomp_segment *h_segs, uint32_t n_segs, const uint32_t *block_len, int variant,
+                uint64_t *n_tiles, uint64_t *plan_bytes) {
+    if ((n_segs && !h_segs) || !block_len || !variant_ok(variant)) return PCOMP_EINVAL;
+    uint64_t nt = 0;
+    for (uint32_t i = 0; i < n_segs; i++) {
+        const int w = (int)h_segs[i].dtype;
+        if (!dtype_ok(w) || (h_segs[i].n && !h_segs[i].ptr) || ((uintptr_t)h_segs[i].ptr % w)) return PCOMP_EINVAL;
+        const uint32_t L = block_len[group_of(w)];
+        if (L == 0 || L > 65535 || (uint64_t)L * w > kTileBytes) return PCOMP_EINVAL;
+        Layout lo;
+        make_layout(h_segs[i].n, w, L, flags_of(variant, L), lo);
+        nt += lo.n_tiles;
+    }
+    if (nt > 0xFFFFFFFFull) return PCOMP_EINVAL;
+    *n_tiles = nt;
+    *plan_bytes = sizeof(BatchPlanHeader) + (uint64_t)n_segs * sizeof(SegDesc) + 4 * ((nt + 1) & ~1ull);
+    return PCOMP_OK;
+}
+
+// Checks a host plan; returns its header or nullptr.
+const BatchPlanHeader *plan_header(const void *h_plan) {
+    if (!h_plan || ((uintptr_t)h_plan & 7)) return nullptr;
+    const BatchPlanHeader *ph = (const BatchPlanHeader *)h_plan;
+    return ph->magic == kPlanMagic ? ph : nullptr;
 }
 
 }  // namespace
@@ -34,13 +77,7 @@ extern "C" size_t pcomp_bound(uint64_t n, pcomp_dtype dtype, uint32_t block_len,
     if (!dtype_ok(w) || block_len == 0 || block_len > 65535 || !variant_ok(variant)) return 0;
     Layout lo;
     make_layout(n, w, block_len, flags_of(variant, block_len), lo);
-    const uint64_t per = 8 / w;  // digits per word of a full-range block: 64 / (8 w)
-    uint64_t words = 0;
-    if (lo.n_blocks) {
-        const uint64_t last = n - (lo.n_blocks - 1) * block_len;
-        words = (lo.n_blocks - 1) * ((block_len + per - 1) / per) + (last + per - 1) / per;
-    }
-    return (size_t)(lo.off_payload + 8 * words);
+    return (size_t)bound_of(lo);
 }
 
 extern "C" size_t pcomp_workspace_size(uint64_t n, pcomp_dtype dtype, uint32_t block_len, int variant) {
@@ -64,8 +101,7 @@ extern "C" int pcomp_compress(const void *d_in, uint64_t n, pcomp_dtype dtype, u
     make_layout(n, w, block_len, flags_of(variant, block_len), lo);
     if (out_capacity < pcomp_bound(n, dtype, block_len, variant)) return PCOMP_ENOSPC;
     if (ws_bytes < ws_bytes_for(lo)) return PCOMP_ENOWS;
-    return launch_compress(d_in, lo, variant, d_out, d_out_size, (uint64_t *)d_ws, ws_bytes / 8,
-                           (hipStream_t)stream);
+    return launch_compress(d_in, lo, variant, d_out, d_out_size, d_ws, (hipStream_t)stream);
 }
 
 extern "C" int pcomp_decompress(const void *d_in, size_t in_size, void *d_out, size_t out_capacity,
@@ -87,4 +123,110 @@ extern "C" int pcomp_stream_info(const void *h_header, uint64_t *n, int *dtype_b
     if (block_len) *block_len = (uint32_t)(h[1] >> 32);
     if (total_bytes) *total_bytes = h[6];
     return PCOMP_OK;
+}
+
+extern "C" size_t pcomp_batch_plan_bytes(const pcomp_segment *h_segs, uint32_t n_segs, const uint32_t *block_len,
+                                         int variant) {
+    uint64_t nt, pb;
+    if (batch_shape(h_segs, n_segs, block_len, variant, &nt, &pb) != PCOMP_OK) return 0;
+    return (size_t)pb;
+}
+
+extern "C" int pcomp_batch_plan(const pcomp_segment *h_segs, uint32_t n_segs, const uint32_t *block_len,
+                                int variant, void *h_plan, size_t plan_bytes) {
+    uint64_t nt, pb;
+    const int rc = batch_shape(h_segs, n_segs, block_len, variant, &nt, &pb);
+    if (rc != PCOMP_OK) return rc;
+    if (variant == PCOMP_SELECT_LEARNED) return PCOMP_ENOMODEL;
+    if (!h_plan || ((uintptr_t)h_plan & 7)) return PCOMP_EINVAL;
+    if (plan_bytes < pb) return PCOMP_ENOSPC;
+    BatchPlanHeader *ph = (BatchPlanHeader *)h_plan;
+    SegDesc *sd = (SegDesc *)(ph + 1);
+    uint32_t *tile_seg = (uint32_t *)(sd + n_segs);
+    *ph = BatchPlanHeader();
+    ph->magic = kPlanMagic;
+    ph->n_segs = n_segs;
+    ph->variant = variant;
+    ph->n_tiles = nt;
+    ph->plan_bytes = pb;
+    // streams in the caller's order, each in a slot of its bound
+    uint64_t off = 0;
+    std::vector<uint64_t> out_off(n_segs);
+    for (uint32_t i = 0; i < n_segs; i++) {
+        const int w = (int)h_segs[i].dtype;
+        const uint32_t L = block_len[group_of(w)];
+        Layout lo;
+        make_layout(h_segs[i].n, w, L, flags_of(variant, L), lo);
+        out_off[i] = off;
+        off += bound_of(lo);
+    }
+    ph->out_bytes = off;
+    // segments and tiles in group order (stable inside a group)
+    uint32_t j = 0;
+    uint64_t t = 0;
+    for (int g = 0; g < 3; g++) {
+        ph->tile_lo[g] = t;
+        const int wg = g == 0 ? 1 : g == 1 ? 2 : 4;
+        for (uint32_t i = 0; i < n_segs; i++) {
+            if ((int)h_segs[i].dtype != wg) continue;
+            const uint32_t L = block_len[g];
+            ph->L[g] = L;
+            SegDesc &d = sd[j];
+            d = SegDesc();
+            d.data = (const uint8_t *)h_segs[i].ptr;
+            d.out_off = out_off[i];
+            make_layout(h_segs[i].n, wg, L, flags_of(variant, L), d.lo);
+            d.tile0 = t;
+            d.user = i;
+            d.group = (uint32_t)g;
+            for (uint64_t k = 0; k < d.lo.n_tiles; k++) tile_seg[t + k] = j;
+            t += d.lo.n_tiles;
+            j++;
+        }
+        ph->tile_hi[g] = t;
+    }
+    if (nt & 1) tile_seg[nt] = 0;
+    ph->ws_bytes = compress_ws_bytes(nt);
+    return PCOMP_OK;
+}
+
+extern "C" int pcomp_batch_info(const void *h_plan, uint64_t *out_bytes, uint64_t *ws_bytes, uint64_t *n_tiles,
+                                uint64_t *h_offsets) {
+    const BatchPlanHeader *ph = plan_header(h_plan);
+    if (!ph) return PCOMP_EINVAL;
+    if (out_bytes) *out_bytes = ph->out_bytes;
+    if (ws_bytes) *ws_bytes = ph->ws_bytes;
+    if (n_tiles) *n_tiles = ph->n_tiles;
+    if (h_offsets) {
+        const SegDesc *sd = (const SegDesc *)(ph + 1);
+        for (uint32_t j = 0; j < ph->n_segs; j++) h_offsets[sd[j].user] = sd[j].out_off;
+    }
+    return PCOMP_OK;
+}
+
+extern "C" int pcomp_compress_batch(const void *h_plan, const void *d_plan, void *d_out, size_t out_capacity,
+                                    uint64_t *d_sizes, void *d_ws, size_t ws_bytes, uint32_t grid, void *stream) {
+    const BatchPlanHeader *ph = plan_header(h_plan);
+    if (!ph || !d_plan || ((uintptr_t)d_plan & 7)) return PCOMP_EINVAL;
+    if ((ph->n_segs && (!d_out || !d_sizes)) || !d_ws || ((uintptr_t)d_out & 7) || ((uintptr_t)d_ws & 7))
+        return PCOMP_EINVAL;
+    if (ph->variant == PCOMP_SELECT_LEARNED) return PCOMP_ENOMODEL;
+    if (out_capacity < ph->out_bytes) return PCOMP_ENOSPC;
+    if (ws_bytes < ph->ws_bytes) return PCOMP_ENOWS;
+    if (ph->n_segs == 0) return PCOMP_OK;
+    const SegDesc *segs = (const SegDesc *)((const BatchPlanHeader *)d_plan + 1);
+    const uint32_t *tile_seg = (const uint32_t *)(segs + ph->n_segs);
+    SegDesc unused = SegDesc();
+    return launch_compress_table(segs, tile_seg, unused, ph->n_segs, ph->tile_lo, ph->tile_hi, ph->L, ph->n_tiles,
+                                 ph->variant, d_out, d_sizes, d_ws, grid, (hipStream_t)stream);
+}
+
+extern "C" int pcomp_decompress_batch(const void *h_plan, const void *d_plan, const void *d_in, size_t in_size,
+                                      int32_t *d_status, uint32_t grid, void *stream) {
+    const BatchPlanHeader *ph = plan_header(h_plan);
+    if (!ph || !d_plan || ((uintptr_t)d_plan & 7) || !d_status) return PCOMP_EINVAL;
+    if ((ph->n_segs && !d_in) || ((uintptr_t)d_in & 7)) return PCOMP_EINVAL;
+    const SegDesc *segs = (const SegDesc *)((const BatchPlanHeader *)d_plan + 1);
+    const uint32_t *tile_seg = (const uint32_t *)(segs + ph->n_segs);
+    return launch_decompress_batch(*ph, segs, tile_seg, d_in, in_size, d_status, grid, (hipStream_t)stream);
 }

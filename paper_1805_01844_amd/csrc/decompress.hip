@@ -21,12 +21,26 @@ struct DecompressArgs {
     DevTables T;
 };
 
+// A batch: the plan's segment table (values go to each segment's `data`), the map from
+// global tile to segment, and the width group of this launch.
+struct BatchDecArgs {
+    const SegDesc *segs;
+    const uint32_t *tile_seg;
+    uint64_t tile_lo, tile_hi;
+    const uint8_t *in;  // the batch buffer: segment streams at their out_off
+    uint64_t in_size;
+    int32_t *status;
+    uint32_t L;         // block length of the group
+    DevTables T;
+};
+
 __device__ __forceinline__ void set_status(int32_t *st, int32_t code) { atomicMin(st, code); }
 
-// Reads and checks the stream header; returns false if it is unusable.
-__device__ bool read_layout(const DecompressArgs &a, Layout &lo, uint64_t &pw, int &fixed) {
-    if (a.in_size < kHdrBytes) return false;
-    const uint64_t *h = (const uint64_t *)a.in;
+// Reads and checks a stream header (in_size bytes are readable); returns false if it is
+// unusable.
+__device__ bool read_layout(const uint8_t *in, uint64_t in_size, Layout &lo, uint64_t &pw, int &fixed) {
+    if (in_size < kHdrBytes) return false;
+    const uint64_t *h = (const uint64_t *)in;
     const uint64_t h0 = h[0], h1 = h[1];
     if ((uint32_t)h0 != kMagic || ((h0 >> 32) & 0xFFFF) != kVersion) return false;
     const uint32_t w = (uint32_t)((h0 >> 48) & 0xFF), flags = (uint32_t)(h0 >> 56);
@@ -39,7 +53,7 @@ __device__ bool read_layout(const DecompressArgs &a, Layout &lo, uint64_t &pw, i
     make_layout(h[2], w, L, flags, lo);
     if (h[3] != lo.n_blocks || (uint32_t)h[4] != lo.tile_blocks) return false;
     pw = h[5];
-    if (pw > (a.in_size >> 3) || h[6] != lo.off_payload + 8 * pw || h[6] > a.in_size) return false;
+    if (pw > (in_size >> 3) || h[6] != lo.off_payload + 8 * pw || h[6] > in_size) return false;
     return true;
 }
 
@@ -129,21 +143,22 @@ __device__ __forceinline__ void unpack_part(const DevTables &T, const SizeCtx &C
     if (i0 == 0) unpack_adv_slow<V>(T, base, n, nwords, src, dst, add);
 }
 
+// Decodes tile `tile` of the stream at `in` (layout lo, pw payload words, fixed class of a
+// single-class stream) into out. Every thread of the workgroup calls it.
 template <int W>
-__device__ void decompress_tiles(const DecompressArgs &a, const Layout &lo, uint64_t pw, int fixed, DecShared &S) {
+__device__ __forceinline__ void decode_tile(const DevTables &T, const uint8_t *in, const Layout &lo, uint64_t pw,
+                                            int fixed, uint64_t tile, uint8_t *out, int32_t *status, DecShared &S) {
     typedef typename Elem<W>::T V;
-    const DevTables &T = a.T;
     const uint32_t tid = threadIdx.x;
     const uint32_t L = lo.L, tb = lo.tile_blocks;
     const uint32_t G = kThreads / tb;
-    const uint64_t *idx = (const uint64_t *)(a.in + lo.off_index);
-    const uint64_t *payload_all = (const uint64_t *)(a.in + lo.off_payload);
+    const uint64_t *idx = (const uint64_t *)(in + lo.off_index);
+    const uint64_t *payload_all = (const uint64_t *)(in + lo.off_payload);
     const uint64_t vmaxw = (1ull << (8 * W)) - 1;
     V *s_val = (V *)S.raw;
     V *s_exc = (V *)S.exc;
     const int neb = (lo.flags & kFlagNe16) ? 2 : 1;
-
-    for (uint64_t tile = blockIdx.x; tile < lo.n_tiles; tile += gridDim.x) {
+    {
         const uint64_t b0 = tile * tb;
         const uint32_t nbt = (uint32_t)min((uint64_t)tb, lo.n_blocks - b0);
         const uint64_t v0 = b0 * L;
@@ -157,10 +172,10 @@ __device__ void decompress_tiles(const DecompressArgs &a, const Layout &lo, uint
         uint32_t nw = 0;
         if (tid < nbt) {
             const uint64_t gb = b0 + tid;
-            const uint32_t bmin = (uint32_t)get_le(a.in + lo.off_min + gb * W, W);
-            const uint32_t rng = (uint32_t)get_le(a.in + lo.off_range + gb * W, W);
-            const int c = (lo.flags & kFlagClass) ? a.in[lo.off_class + gb] : fixed;
-            const uint32_t ne = (lo.flags & kFlagNe) ? (uint32_t)get_le(a.in + lo.off_ne + gb * neb, neb) : 0;
+            const uint32_t bmin = (uint32_t)get_le(in + lo.off_min + gb * W, W);
+            const uint32_t rng = (uint32_t)get_le(in + lo.off_range + gb * W, W);
+            const int c = (lo.flags & kFlagClass) ? in[lo.off_class + gb] : fixed;
+            const uint32_t ne = (lo.flags & kFlagNe) ? (uint32_t)get_le(in + lo.off_ne + gb * neb, neb) : 0;
             const uint32_t Lb = (uint32_t)min((uint64_t)L, lo.n - gb * L);
             const uint64_t B = (uint64_t)rng + 1;
             const uint32_t beta = bitlen64(B - 1);
@@ -181,9 +196,9 @@ __device__ void decompress_tiles(const DecompressArgs &a, const Layout &lo, uint
         if (tid == 0) S.off[nbt] = tile_words;
         __syncthreads();
         if (S.bad || base_off > pw || next_off > pw || next_off != base_off + tile_words) {
-            if (tid == 0) set_status(a.status, PCOMP_ECORRUPT);
+            if (tid == 0) set_status(status, PCOMP_ECORRUPT);
             __syncthreads();
-            continue;
+            return;
         }
         const uint64_t *payload = payload_all + base_off;
 
@@ -249,7 +264,7 @@ __device__ void decompress_tiles(const DecompressArgs &a, const Layout &lo, uint
         // ---- 4. coalesced store of the tile (16-byte stores where the output is aligned)
         {
             const uint8_t *sb = (const uint8_t *)S.raw;
-            uint8_t *gdst = a.out + v0 * W;
+            uint8_t *gdst = out + v0 * W;
             const uint32_t head = (uint32_t)((16 - ((uintptr_t)gdst & 15)) & 15);
             const uint32_t nbytes = nvt * W;
             const uint32_t hb = head < nbytes ? head : nbytes;
@@ -279,7 +294,7 @@ __global__ __launch_bounds__(kThreads) void decompress_kernel(DecompressArgs a) 
     Layout lo;
     uint64_t pw;
     int fixed;
-    const bool ok = read_layout(a, lo, pw, fixed);
+    const bool ok = read_layout(a.in, a.in_size, lo, pw, fixed);
     if (W == 1 && !ok) {  // reported once, by the width-1 kernel
         if (blockIdx.x == 0 && threadIdx.x == 0) set_status(a.status, PCOMP_ECORRUPT);
         return;
@@ -295,7 +310,31 @@ __global__ __launch_bounds__(kThreads) void decompress_kernel(DecompressArgs a) 
     }
     fill_size_ctx(a.T, lo.L, S.C);
     __syncthreads();
-    decompress_tiles<W>(a, lo, pw, fixed, S);
+    for (uint64_t tile = blockIdx.x; tile < lo.n_tiles; tile += gridDim.x)
+        decode_tile<W>(a.T, a.in, lo, pw, fixed, tile, a.out, a.status, S);
+}
+
+// Batch: the tiles of one width group, each decoded into its segment's destination. A
+// segment whose stream header disagrees with the plan is reported corrupt and skipped.
+template <int W>
+__global__ __launch_bounds__(kThreads) void decompress_batch_kernel(BatchDecArgs a) {
+    __shared__ DecShared S;
+    fill_size_ctx(a.T, a.L, S.C);
+    __syncthreads();
+    for (uint64_t gt = a.tile_lo + blockIdx.x; gt < a.tile_hi; gt += gridDim.x) {
+        const SegDesc sd = uniform_seg(a.segs[uni32(a.tile_seg[gt])]);
+        const uint8_t *s = a.in + sd.out_off;
+        Layout lo;
+        uint64_t pw;
+        int fixed;
+        const bool ok = sd.out_off < a.in_size && read_layout(s, a.in_size - sd.out_off, lo, pw, fixed) &&
+                        lo.w == W && lo.n == sd.lo.n && lo.L == sd.lo.L && lo.flags == sd.lo.flags;
+        if (!ok) {
+            if (threadIdx.x == 0) set_status(a.status, PCOMP_ECORRUPT);
+            continue;
+        }
+        decode_tile<W>(a.T, s, lo, pw, fixed, gt - sd.tile0, (uint8_t *)sd.data, a.status, S);
+    }
 }
 
 __global__ void set_i32_kernel(int32_t *p, int32_t v) { *p = v; }
@@ -316,6 +355,37 @@ int launch_decompress(const void *d_in, size_t in_size, void *d_out, size_t out_
     decompress_kernel<1><<<grid, kThreads, 0, st>>>(a);
     decompress_kernel<2><<<grid, kThreads, 0, st>>>(a);
     decompress_kernel<4><<<grid, kThreads, 0, st>>>(a);
+    return hipGetLastError() == hipSuccess ? PCOMP_OK : PCOMP_EHIP;
+}
+
+// Batch decompression: one persistent launch per width group present. grid = 0 picks 4096
+// workgroups (or one per tile when there are fewer tiles).
+int launch_decompress_batch(const BatchPlanHeader &ph, const SegDesc *d_segs, const uint32_t *d_tile_seg,
+                            const void *d_in, size_t in_size, int32_t *d_status, uint32_t grid, hipStream_t st) {
+    BatchDecArgs a;
+    if (tables_for_current_device(&a.T) != PCOMP_OK) return PCOMP_EHIP;
+    set_i32_kernel<<<1, 1, 0, st>>>(d_status, PCOMP_OK);
+    a.segs = d_segs;
+    a.tile_seg = d_tile_seg;
+    a.in = (const uint8_t *)d_in;
+    a.in_size = in_size;
+    a.status = d_status;
+    for (int g = 0; g < 3; g++) {
+        const uint64_t ntg = ph.tile_hi[g] - ph.tile_lo[g];
+        if (!ntg) continue;
+        BatchDecArgs b = a;
+        b.tile_lo = ph.tile_lo[g];
+        b.tile_hi = ph.tile_hi[g];
+        b.L = ph.L[g];
+        const uint32_t want = grid ? grid : 4096;
+        const uint32_t gg = (uint32_t)(ntg < want ? ntg : want);
+        if (g == 0)
+            decompress_batch_kernel<1><<<gg, kThreads, 0, st>>>(b);
+        else if (g == 1)
+            decompress_batch_kernel<2><<<gg, kThreads, 0, st>>>(b);
+        else
+            decompress_batch_kernel<4><<<gg, kThreads, 0, st>>>(b);
+    }
     return hipGetLastError() == hipSuccess ? PCOMP_OK : PCOMP_EHIP;
 }
 

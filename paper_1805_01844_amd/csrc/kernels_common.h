@@ -90,6 +90,35 @@ __device__ __forceinline__ uint32_t wg_excl_scan(uint32_t x, uint32_t *scratch, 
     return inc - x + add;
 }
 
+// Scalar-register copies of values that every lane of the wavefront holds equally (segment
+// descriptors read from memory): keeps them out of vector registers.
+__device__ __forceinline__ uint32_t uni32(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ uint64_t uni64(uint64_t x) {
+    return ((uint64_t)uni32((uint32_t)(x >> 32)) << 32) | uni32((uint32_t)x);
+}
+__device__ __forceinline__ SegDesc uniform_seg(const SegDesc &s) {
+    SegDesc u;
+    u.data = (const uint8_t *)uni64((uint64_t)(uintptr_t)s.data);
+    u.out_off = uni64(s.out_off);
+    u.lo.n = uni64(s.lo.n);
+    u.lo.n_blocks = uni64(s.lo.n_blocks);
+    u.lo.n_tiles = uni64(s.lo.n_tiles);
+    u.lo.L = uni32(s.lo.L);
+    u.lo.w = uni32(s.lo.w);
+    u.lo.tile_blocks = uni32(s.lo.tile_blocks);
+    u.lo.flags = uni32(s.lo.flags);
+    u.lo.off_index = uni64(s.lo.off_index);
+    u.lo.off_min = uni64(s.lo.off_min);
+    u.lo.off_range = uni64(s.lo.off_range);
+    u.lo.off_class = uni64(s.lo.off_class);
+    u.lo.off_ne = uni64(s.lo.off_ne);
+    u.lo.off_payload = uni64(s.lo.off_payload);
+    u.tile0 = uni64(s.tile0);
+    u.user = uni32(s.user);
+    u.group = uni32(s.group);
+    return u;
+}
+
 struct MinOp {
     __device__ uint32_t operator()(uint32_t a, uint32_t b) const { return a < b ? a : b; }
     __device__ uint64_t operator()(uint64_t a, uint64_t b) const { return a < b ? a : b; }

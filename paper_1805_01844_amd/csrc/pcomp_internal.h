@@ -114,6 +114,34 @@ __host__ __device__ inline void make_layout(uint64_t n, uint32_t w, uint32_t L, 
     lo.off_payload = (o + 7) & ~(uint64_t)7;
 }
 
+// One stream of a call: its values, where its stream sits in the output, and its tiles.
+// A batch is a table of these, grouped by element width (one group per launch); a single
+// call is a table of one. For decompression `data` is the destination of the values.
+struct SegDesc {
+    const uint8_t *data;  // the segment's values (compress: read; decompress: written)
+    uint64_t out_off;     // byte offset of the segment's stream in the batch buffer (8-aligned)
+    Layout lo;
+    uint64_t tile0;       // global index of the segment's first tile
+    uint32_t user;        // position of the segment in the caller's list
+    uint32_t group;       // element-width group: 0 u8, 1 u16, 2 u32
+};
+
+// Host-built plan of a batch: this header, then n_segs SegDesc in group order (the groups'
+// global tiles are consecutive), then the segment of every global tile (u32 each).
+struct BatchPlanHeader {
+    uint64_t magic;                  // kPlanMagic
+    uint32_t n_segs;
+    int32_t variant;
+    uint64_t n_tiles;                // tiles of the whole batch
+    uint64_t out_bytes;              // batch buffer bytes: the sum of the segments' bounds
+    uint64_t ws_bytes;               // workspace bytes
+    uint64_t plan_bytes;             // bytes of the whole plan
+    uint64_t tile_lo[3], tile_hi[3]; // global tiles of each group (0 u8, 1 u16, 2 u32)
+    uint32_t L[3];                   // block length of each group (0: group empty)
+    uint32_t pad;
+};
+constexpr uint64_t kPlanMagic = 0x4E414C5042504350ull;  // "PCPBPLAN"
+
 // Host side: tables of the current device (built on first use).
 int tables_for_current_device(DevTables *out);
 

@@ -94,3 +94,50 @@ def test_cycle_form_word_counts_match_oracle(pc, orc):
         for n in [1, 2, 5, 13, 14, 40, 41, 154, 1000, 1024, 4096, 65535]:
             assert L.pcomp_atlas_words(B, n, ctypes.byref(out)) == 0
             assert out.value == orc.adv_words(n, B), (B, n)
+
+
+def _segs(pc, spec):
+    arr = (pc._Segment * len(spec))()
+    for i, (w, n) in enumerate(spec):
+        arr[i] = pc._Segment(0x10000 * (i + 1), n, w, 0)  # plans record pointers, never read them
+    return arr
+
+
+def test_batch_plan_slots_and_tiles(pc, orc):
+    """Streams sit in the caller's order, each in a slot of its bound; tiles are counted per
+    segment with the segment's own tile size."""
+    spec = [(2, 74200), (4, 3000), (2, 0), (1, 777), (2, 1), (4, 50000), (1, 0)]
+    Ls = (300, 40, 1000)
+    for variant in (0, 8, 5, 0x100):
+        segs = _segs(pc, spec)
+        L3 = (ctypes.c_uint32 * 3)(*Ls)
+        nb = pc.lib().pcomp_batch_plan_bytes(segs, len(spec), L3, variant)
+        assert nb > 0
+        buf = (ctypes.c_uint64 * (nb // 8 + 1))()
+        assert pc.lib().pcomp_batch_plan(segs, len(spec), L3, variant, buf, nb) == 0
+        assert pc.lib().pcomp_batch_plan(segs, len(spec), L3, variant, buf, nb - 8) == pc.ENOSPC
+        ob, wb, nt = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+        offs = (ctypes.c_uint64 * len(spec))()
+        assert pc.lib().pcomp_batch_info(buf, ctypes.byref(ob), ctypes.byref(wb), ctypes.byref(nt), offs) == 0
+        off, tiles = 0, 0
+        for i, (w, n) in enumerate(spec):
+            L = Ls[{1: 0, 2: 1, 4: 2}[w]]
+            assert offs[i] == off
+            off += orc.bound(n, w, L, variant)
+            nblk = (n + L - 1) // L
+            tb = orc.tile_blocks(L, w)
+            tiles += (nblk + tb - 1) // tb
+        assert ob.value == off and nt.value == tiles
+        assert wb.value >= 8 + 12 * tiles
+
+
+def test_batch_plan_rejects_bad_arguments(pc):
+    L3 = (ctypes.c_uint32 * 3)(1024, 1024, 1024)
+    assert pc.lib().pcomp_batch_plan_bytes(_segs(pc, [(3, 10)]), 1, L3, 0) == 0   # bad dtype
+    assert pc.lib().pcomp_batch_plan_bytes(_segs(pc, [(2, 10)]), 1, L3, 16) == 0  # bad variant
+    big = (ctypes.c_uint32 * 3)(1024, 8193, 1024)  # u16 blocks over the 16 KiB tile
+    assert pc.lib().pcomp_batch_plan_bytes(_segs(pc, [(2, 10)]), 1, big, 0) == 0
+    # an unused group's block length is not checked
+    assert pc.lib().pcomp_batch_plan_bytes(_segs(pc, [(1, 10)]), 1, big, 0) > 0
+    buf = (ctypes.c_uint64 * 8)()
+    assert pc.lib().pcomp_batch_info(buf, None, None, None, None) == pc.EINVAL  # not a plan
