@@ -35,7 +35,7 @@ def build(force: bool = False) -> str:
     """Compiles the oracle with gcc -O2 (plain scalar C, no intrinsics)."""
     if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
         tmp = _LIB_PATH + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-shared", "-fPIC", "-o", tmp, _SRC])
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
 
@@ -82,6 +82,16 @@ def lib():
         L.orc_block_facts.argtypes = [vp, u64, c_int, u32, c_int, vp, vp, vp, vp, vp, vp]
         L.orc_all_class_words.restype = None
         L.orc_all_class_words.argtypes = [vp, u64, u64, vp, vp]
+        L.orc_set_model.restype = c_int
+        L.orc_set_model.argtypes = [vp, u64]
+        L.orc_block_features.restype = None
+        L.orc_block_features.argtypes = [vp, u64, u64, u64, vp]
+        L.orc_mlp_scores.restype = None
+        L.orc_mlp_scores.argtypes = [vp, vp, vp]
+        L.orc_mlp_predict.restype = c_int
+        L.orc_mlp_predict.argtypes = [vp, vp]
+        L.orc_features.restype = c_int
+        L.orc_features.argtypes = [vp, u64, c_int, u32, vp, vp]
         _lib = L
     return _lib
 
@@ -250,3 +260,54 @@ def block_facts(x: np.ndarray, L: int, variant: int, forced=None):
     if rc:
         raise ValueError("block_facts failed: %d" % rc)
     return {k: v[:nb] for k, v in arrs.items()}
+
+
+# ---- learned selector (binary32, bit-exact definition) ---------------------------
+
+MLP_IN, MLP_HID, MLP_OUT = 19, 64, 16
+MLP_PARAMS = MLP_HID * MLP_IN + MLP_HID + MLP_OUT * MLP_HID + MLP_OUT
+
+
+def set_model(params) -> None:
+    """Loads the selector's 2320 parameters (None unloads)."""
+    if params is None:
+        lib().orc_set_model(None, 0)
+        return
+    p = np.ascontiguousarray(np.asarray(params, dtype=np.float32))
+    if lib().orc_set_model(_ptr(p), p.size) != 0:
+        raise ValueError("model needs %d floats" % MLP_PARAMS)
+
+
+def block_features(digits, vmin: int, vmax: int) -> np.ndarray:
+    d = _u64(digits)
+    x = np.zeros(MLP_IN, dtype=np.float32)
+    lib().orc_block_features(_ptr(d), d.size, vmin, vmax, _ptr(x))
+    return x
+
+
+def features(x: np.ndarray, L: int, with_words: bool = True):
+    """(features [n_blocks, 19] float32, class sizes [n_blocks, 16] uint64 or None) of an array."""
+    x = np.ascontiguousarray(x)
+    w = _WIDTH[x.dtype]
+    nb = (x.size + L - 1) // L
+    f = np.zeros((max(nb, 1), MLP_IN), dtype=np.float32)
+    words = np.zeros((max(nb, 1), 16), dtype=np.uint64) if with_words else None
+    rc = lib().orc_features(_ptr(x), x.size, w, L, _ptr(f), _ptr(words) if with_words else None)
+    if rc:
+        raise ValueError("features failed: %d" % rc)
+    return f[:nb], (words[:nb] if with_words else None)
+
+
+def mlp_scores(params, x) -> np.ndarray:
+    p = np.ascontiguousarray(np.asarray(params, dtype=np.float32))
+    xs = np.ascontiguousarray(np.asarray(x, dtype=np.float32)).reshape(-1, MLP_IN)
+    out = np.zeros((xs.shape[0], MLP_OUT), dtype=np.float32)
+    for i in range(xs.shape[0]):
+        lib().orc_mlp_scores(_ptr(p), ctypes.c_void_p(xs.ctypes.data + 4 * MLP_IN * i),
+                             ctypes.c_void_p(out.ctypes.data + 4 * MLP_OUT * i))
+    return out
+
+
+def mlp_predict(params, x) -> np.ndarray:
+    s = mlp_scores(params, x)
+    return np.argmax(s, axis=1).astype(np.uint8)  # first index of the maximum

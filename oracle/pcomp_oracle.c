@@ -26,6 +26,7 @@
  * rule of the series, the threshold/excess classes, the stream layout) are the
  * ones listed in the design notes; each is restated next to the code it shapes.
  */
+#include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -385,7 +386,99 @@ void orc_class_unpack(int cls, const uint64_t *words, uint64_t n, uint64_t B, ui
 /*   kept only if it is valid and strictly smaller than basic t = 0;         */
 /*   else the block falls back to class 0 (basic, t = 0).                    */
 /* ---------------------------------------------------------------------- */
-static int choose_class(int variant, int forced, const uint64_t *d, uint64_t n, uint64_t B)
+/* ---------------------------------------------------------------------- */
+/* Learned class selector (an addition to the method: the paper chooses the */
+/* variant by hand for a whole file, Sec. 4). A small network reads 19     */
+/* features of a block and scores the 16 classes; the best-scoring class is */
+/* then kept under the same rule as a fixed class.                          */
+/*                                                                          */
+/* Features, all in binary32 with correctly rounded operations only, so    */
+/* that any IEEE implementation obtains the same bits:                      */
+/*   x[b], b = 0..15: H[b] / L_b, H[b] = #{j : min(beta - bitlen(d_j), 15)  */
+/*          = b}, beta = bitlen(B - 1) (digits by octave below the top);    */
+/*   x[16]: lg(min + 1) / 32, x[17]: lg(max + 1) / 32, lg the piecewise-    */
+/*          linear base-2 logarithm: for 2^e <= u < 2^(e+1),                */
+/*          lg(u) = e + (u - 2^e) 2^-e, with (u - 2^e) rounded to binary32; */
+/*   x[18]: L_b / 4096.                                                     */
+/* Network: h_j = relu(b1_j + sum_i W1[j][i] x_i), j < 64;                 */
+/* s_k = b2_k + sum_j W2[k][j] h_j, k < 16; each sum taken in index order   */
+/* as a chain of fused multiply-adds starting from the bias. Parameters, in */
+/* this order: W1 (64 x 19, row-major), b1 (64), W2 (16 x 64), b2 (16):     */
+/* 2320 floats. The predicted class is the first index of the largest s_k. */
+/* ---------------------------------------------------------------------- */
+#define ORC_MLP_IN 19
+#define ORC_MLP_HID 64
+#define ORC_MLP_OUT 16
+#define ORC_MLP_PARAMS (ORC_MLP_HID * ORC_MLP_IN + ORC_MLP_HID + ORC_MLP_OUT * ORC_MLP_HID + ORC_MLP_OUT)
+
+static float g_model[ORC_MLP_PARAMS];
+static int g_have_model = 0;
+
+int orc_set_model(const float *w, uint64_t n)
+{
+    if (!w) {
+        g_have_model = 0;
+        return ORC_OK;
+    }
+    if (n != ORC_MLP_PARAMS) return ORC_EINVAL;
+    memcpy(g_model, w, sizeof(g_model));
+    g_have_model = 1;
+    return ORC_OK;
+}
+
+static float lg_f32(uint64_t u) /* u >= 1 */
+{
+    int e = bitlen64(u) - 1;
+    float frac = ldexpf((float)(uint32_t)(u - ((uint64_t)1 << e)), -e);
+    return (float)e + frac;
+}
+
+
+void orc_block_features(const uint64_t *d, uint64_t n, uint64_t vmin, uint64_t vmax, float *x)
+{
+    uint64_t H[16] = {0};
+    int beta = bitlen64(vmax - vmin);
+    for (uint64_t j = 0; j < n; j++) {
+        int b = beta - bitlen64(d[j]);
+        H[b < 15 ? b : 15]++;
+    }
+    for (int b = 0; b < 16; b++) x[b] = (float)H[b] / (float)n;
+    x[16] = lg_f32(vmin + 1) * 0.03125f;
+    x[17] = lg_f32(vmax + 1) * 0.03125f;
+    x[18] = (float)n * (1.0f / 4096.0f);
+}
+
+void orc_mlp_scores(const float *model, const float *x, float *s)
+{
+    const float *W1 = model, *b1 = W1 + ORC_MLP_HID * ORC_MLP_IN, *W2 = b1 + ORC_MLP_HID, *b2 = W2 + ORC_MLP_OUT * ORC_MLP_HID;
+    float h[ORC_MLP_HID];
+    for (int j = 0; j < ORC_MLP_HID; j++) {
+        float a = b1[j];
+        for (int i = 0; i < ORC_MLP_IN; i++) a = fmaf(W1[j * ORC_MLP_IN + i], x[i], a);
+        h[j] = a > 0.0f ? a : 0.0f;
+    }
+    for (int k = 0; k < ORC_MLP_OUT; k++) {
+        float a = b2[k];
+        for (int j = 0; j < ORC_MLP_HID; j++) a = fmaf(W2[k * ORC_MLP_HID + j], h[j], a);
+        s[k] = a;
+    }
+}
+
+int orc_mlp_predict(const float *model, const float *x)
+{
+    float s[ORC_MLP_OUT];
+    orc_mlp_scores(model, x, s);
+    int best = 0;
+    for (int k = 1; k < ORC_MLP_OUT; k++)
+        if (s[k] > s[best]) best = k;
+    return best;
+}
+
+/* Class of one block. Fixed t = 0 classes are taken as given; exhaustive is the
+ * smallest valid class (ties to the lowest id); a fixed t > 0 class or the
+ * learned prediction is kept only if valid and strictly smaller than class 0.
+ * forced >= 0 replaces the learned prediction. */
+static int choose_class(int variant, int forced, const uint64_t *d, uint64_t n, uint64_t B, uint64_t vmin)
 {
     if (variant == 0 || variant == 8) return variant;
     uint64_t w0 = orc_class_words(0, d, n, B, NULL);
@@ -403,7 +496,17 @@ static int choose_class(int variant, int forced, const uint64_t *d, uint64_t n, 
         }
         return cand;
     }
-    cand = (variant == ORC_SELECT_LEARNED) ? forced : variant;
+    if (variant == ORC_SELECT_LEARNED) {
+        if (forced >= 0) {
+            cand = forced;
+        } else {
+            float x[ORC_MLP_IN];
+            orc_block_features(d, n, vmin, vmin + B - 1, x);
+            cand = orc_mlp_predict(g_model, x);
+        }
+    } else {
+        cand = variant;
+    }
     if (!orc_class_valid(cand, B)) return 0;
     if (orc_class_words(cand, d, n, B, NULL) < w0) return cand;
     return 0;
@@ -523,7 +626,7 @@ int64_t orc_compress(const void *in, uint64_t n, int w, uint32_t L, int variant,
 {
     if (!(w == 1 || w == 2 || w == 4) || L == 0 || L > 65535 || !variant_ok(variant)) return ORC_EINVAL;
     if (n && !in) return ORC_EINVAL;
-    if (variant == ORC_SELECT_LEARNED && n && !forced) return ORC_ENOMODEL;
+    if (variant == ORC_SELECT_LEARNED && n && !forced && !g_have_model) return ORC_ENOMODEL;
     orc_layout lo;
     unsigned flags = stream_flags(variant, L);
     layout_of(n, w, L, flags, &lo);
@@ -549,7 +652,7 @@ int64_t orc_compress(const void *in, uint64_t n, int w, uint32_t L, int variant,
         }
         uint64_t B = vmax - vmin + 1; /* Sec. 3.1: B = v_max - v_min + 1 */
         for (uint64_t j = 0; j < Lb; j++) d[j] = load_val(in, w, first + j) - vmin;
-        int c = choose_class(variant, forced ? forced[b] : 0, d, Lb, B);
+        int c = choose_class(variant, forced ? forced[b] : -1, d, Lb, B, vmin);
         uint64_t ne = 0;
         uint64_t nw = orc_class_words(c, d, Lb, B, &ne);
         mins[b] = vmin;
@@ -694,6 +797,7 @@ int orc_block_facts(const void *in, uint64_t n, int w, uint32_t L, int variant, 
                     uint64_t *mins, uint64_t *Bs, uint8_t *cls, uint64_t *nes, uint64_t *nws)
 {
     if (!(w == 1 || w == 2 || w == 4) || L == 0 || !variant_ok(variant)) return ORC_EINVAL;
+    if (variant == ORC_SELECT_LEARNED && n && !forced && !g_have_model) return ORC_ENOMODEL;
     uint64_t nb = (n + L - 1) / L;
     uint64_t *d = (uint64_t *)malloc(sizeof(uint64_t) * L);
     for (uint64_t b = 0; b < nb; b++) {
@@ -707,7 +811,7 @@ int orc_block_facts(const void *in, uint64_t n, int w, uint32_t L, int variant, 
         }
         uint64_t B = vmax - vmin + 1;
         for (uint64_t j = 0; j < Lb; j++) d[j] = load_val(in, w, first + j) - vmin;
-        int c = choose_class(variant, forced ? forced[b] : 0, d, Lb, B);
+        int c = choose_class(variant, forced ? forced[b] : -1, d, Lb, B, vmin);
         uint64_t ne = 0;
         uint64_t nw = orc_class_words(c, d, Lb, B, &ne);
         if (mins) mins[b] = vmin;
@@ -731,4 +835,29 @@ void orc_all_class_words(const uint64_t *d, uint64_t n, uint64_t B, uint64_t *wo
         }
         words16[c] = orc_class_words(c, d, n, B, &ne16[c]);
     }
+}
+
+/* Features (19 floats per block, as the learned selector reads them) and the
+ * sizes of all 16 classes (UINT64_MAX when invalid) of every block of an array. */
+int orc_features(const void *in, uint64_t n, int w, uint32_t L, float *x, uint64_t *words16)
+{
+    if (!(w == 1 || w == 2 || w == 4) || L == 0) return ORC_EINVAL;
+    uint64_t nb = (n + L - 1) / L;
+    uint64_t *d = (uint64_t *)malloc(sizeof(uint64_t) * L);
+    uint64_t ne16[16];
+    for (uint64_t b = 0; b < nb; b++) {
+        uint64_t first = b * L;
+        uint64_t Lb = (n - first < L) ? (n - first) : L;
+        uint64_t vmin = UINT64_MAX, vmax = 0;
+        for (uint64_t j = 0; j < Lb; j++) {
+            uint64_t v = load_val(in, w, first + j);
+            if (v < vmin) vmin = v;
+            if (v > vmax) vmax = v;
+        }
+        for (uint64_t j = 0; j < Lb; j++) d[j] = load_val(in, w, first + j) - vmin;
+        if (x) orc_block_features(d, Lb, vmin, vmax, x + ORC_MLP_IN * b);
+        if (words16) orc_all_class_words(d, Lb, vmax - vmin + 1, words16 + 16 * b, ne16);
+    }
+    free(d);
+    return 0;
 }
