@@ -71,7 +71,8 @@ typedef enum { PCOMP_U8 = 1, PCOMP_U16 = 2, PCOMP_U32 = 4 } pcomp_dtype;
  *   PCOMP_SELECT_EXHAUSTIVE: per block, the smallest of the 16 classes (ties to
  *          the lowest id).
  *   PCOMP_SELECT_LEARNED: per block, the class predicted by the network loaded
- *          with pcomp_set_model(), kept only if valid and smaller than class 0. */
+ *          with pcomp_set_model(), kept only if valid and strictly smaller than
+ *          class 0 (PCOMP_ENOMODEL when no network is loaded on the device). */
 #define PCOMP_CLASS(family, t) ((family) * 8 + (t))
 #define PCOMP_SELECT_EXHAUSTIVE 0x100
 #define PCOMP_SELECT_LEARNED 0x200
@@ -179,6 +180,56 @@ int pcomp_compress_batch(const void *h_plan, const void *d_plan, void *d_out, si
  * No workspace is needed. */
 int pcomp_decompress_batch(const void *h_plan, const void *d_plan, const void *d_in, size_t in_size,
                            int32_t *d_status, uint32_t grid, void *stream);
+
+/* ---- Learned class selector ----------------------------------------------------
+ * The method leaves the choice of packing to the user (basic or advanced, Sec. 3.1-3.2;
+ * the paper compares them per file, Sec. 4). PCOMP_SELECT_LEARNED picks a class per
+ * block with a small network instead of sizing all 16: 19 features of the block -> 64
+ * ReLU units -> 16 class scores, the first largest score wins, and the class is kept
+ * only if valid and strictly smaller than class 0 (so output stays lossless and never
+ * larger than the plain basic method).
+ *
+ * Features, computed with correctly rounded binary32 operations only (every IEEE
+ * implementation gets the same bits): for b = 0..15, H[b] / L_b with H[b] the number
+ * of digits d = v - min with min(bitlen(B - 1) - bitlen(d), 15) = b; lg(min + 1) / 32;
+ * lg(max + 1) / 32, where lg(u) = e + (u - 2^e) 2^-e for 2^e <= u < 2^(e+1) (the
+ * difference rounded to binary32); and L_b / 4096. Every sum of the network is a chain
+ * of fused multiply-adds in index order starting from the bias. Parameters (2320
+ * floats, in this order): W1 (64 x 19, row-major), b1 (64), W2 (16 x 64), b2 (16). */
+#define PCOMP_MLP_PARAMS 2320
+
+/* Loads the selector's parameters (host array of PCOMP_MLP_PARAMS floats; NULL
+ * unloads) on the current device. Synchronous; must not overlap a learned
+ * compression on that device. Returns PCOMP_OK, PCOMP_EINVAL or PCOMP_EHIP. */
+int pcomp_set_model(const float *h_params, size_t n_floats);
+
+/* Training data: for every block of an array (blocks of block_len as in
+ * pcomp_compress), its 19 features (d_x, float [n_blocks][19]), the words of each
+ * of the 16 classes (d_words, u32 [n_blocks][16], 0xFFFFFFFF when the class is
+ * invalid) and the class exhaustive search picks (d_label, u8 [n_blocks]). Any of
+ * the three outputs may be NULL. d_ws: 1024 bytes of device workspace. */
+int pcomp_block_features(const void *d_in, uint64_t n, pcomp_dtype dtype, uint32_t block_len, float *d_x,
+                         uint32_t *d_words, uint8_t *d_label, void *d_ws, size_t ws_bytes, void *stream);
+
+/* Scores (d_scores, float [n][16]) of n feature vectors (d_x, float [n][19]) under
+ * the parameters at d_params, with the selector's exact order of operations. */
+int pcomp_mlp_scores(const float *d_params, const float *d_x, uint64_t n, float *d_scores, void *stream);
+
+/* Host-only. Workspace bytes of pcomp_mlp_loss_grad for n samples. */
+size_t pcomp_mlp_workspace_size(uint64_t n);
+
+/* Mean cross-entropy of softmax(scores) against the labels (u8 class ids) over n
+ * samples, written to *d_loss (device float, may be NULL), and its gradient with
+ * respect to the parameters (d_grad, PCOMP_MLP_PARAMS floats). Deterministic: the
+ * same inputs give the same bits. */
+int pcomp_mlp_loss_grad(const float *d_params, const float *d_x, const uint8_t *d_labels, uint64_t n, float *d_grad,
+                        float *d_loss, void *d_ws, size_t ws_bytes, void *stream);
+
+/* One Adam step (Kingma & Ba, 2015, with bias correction; step counts from 1) on
+ * the parameters, with moment buffers d_m and d_v (PCOMP_MLP_PARAMS floats each,
+ * zero before the first step). */
+int pcomp_mlp_adam(float *d_params, const float *d_grad, float *d_m, float *d_v, uint32_t step, float lr,
+                   float beta1, float beta2, float eps, void *stream);
 
 #ifdef __cplusplus
 }

@@ -67,6 +67,19 @@ def lib():
         L.pcomp_compress_batch.argtypes = [vp, vp, vp, sz, vp, vp, sz, u32, vp]
         L.pcomp_decompress_batch.restype = i32
         L.pcomp_decompress_batch.argtypes = [vp, vp, vp, sz, vp, u32, vp]
+        L.pcomp_set_model.restype = i32
+        L.pcomp_set_model.argtypes = [vp, sz]
+        L.pcomp_block_features.restype = i32
+        L.pcomp_block_features.argtypes = [vp, u64, i32, u32, vp, vp, vp, vp, sz, vp]
+        L.pcomp_mlp_scores.restype = i32
+        L.pcomp_mlp_scores.argtypes = [vp, vp, u64, vp, vp]
+        L.pcomp_mlp_workspace_size.restype = sz
+        L.pcomp_mlp_workspace_size.argtypes = [u64]
+        L.pcomp_mlp_loss_grad.restype = i32
+        L.pcomp_mlp_loss_grad.argtypes = [vp, vp, vp, u64, vp, vp, vp, sz, vp]
+        L.pcomp_mlp_adam.restype = i32
+        L.pcomp_mlp_adam.argtypes = [vp, vp, vp, vp, u32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                     ctypes.c_float, vp]
         _lib = L
     return _lib
 
@@ -300,3 +313,76 @@ class BatchDecoder:
         st = int(self.status.item())
         if st != OK:
             raise PcompError(st, "pcomp_decompress_batch (device status)")
+
+
+# ---- learned class selector -----------------------------------------------------------
+
+MLP_PARAMS = 2320
+MLP_IN, MLP_OUT = 19, 16
+
+
+def _vp(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def set_model(params) -> None:
+    """Loads the selector's parameters (2320 floats: tensor, array or sequence; None
+    unloads) on the current device."""
+    if params is None:
+        _check(lib().pcomp_set_model(None, 0), "pcomp_set_model")
+        return
+    p = torch.as_tensor(params, dtype=torch.float32).detach().cpu().contiguous().reshape(-1)
+    _check(lib().pcomp_set_model(ctypes.c_void_p(p.data_ptr()), p.numel()), "pcomp_set_model")
+
+
+def block_features(x: torch.Tensor, block_len: int, want_x=True, want_words=True, want_label=True):
+    """(features [nb, 19] f32, class words [nb, 16] u32-as-int32, labels [nb] u8) of a CUDA
+    array, computed on the GPU; entries not wanted are None."""
+    x = x.contiguous().reshape(-1)
+    n, w = x.numel(), _DT[x.dtype]
+    nb = (n + block_len - 1) // block_len
+    dev = x.device
+    fx = torch.empty((max(nb, 1), MLP_IN), dtype=torch.float32, device=dev) if want_x else None
+    words = torch.empty((max(nb, 1), 16), dtype=torch.int32, device=dev) if want_words else None
+    lab = torch.empty(max(nb, 1), dtype=torch.uint8, device=dev) if want_label else None
+    ws = torch.empty(1024, dtype=torch.uint8, device=dev)
+    rc = lib().pcomp_block_features(_vp(x), n, w, block_len, _vp(fx), _vp(words), _vp(lab), _vp(ws), ws.numel(),
+                                    _stream_handle())
+    _check(rc, "pcomp_block_features")
+    cut = lambda t: None if t is None else t[:nb]
+    return cut(fx), cut(words), cut(lab)
+
+
+def mlp_scores(params: torch.Tensor, X: torch.Tensor) -> torch.Tensor:
+    n = X.shape[0]
+    S = torch.empty((max(n, 1), MLP_OUT), dtype=torch.float32, device=X.device)
+    _check(lib().pcomp_mlp_scores(_vp(params), _vp(X), n, _vp(S), _stream_handle()), "pcomp_mlp_scores")
+    return S[:n]
+
+
+class MLPTrainer:
+    """Adam training of the selector on the GPU through the library's kernels."""
+
+    def __init__(self, params: torch.Tensor, max_batch: int, lr=3e-3, betas=(0.9, 0.999), eps=1e-8):
+        self.params = params.detach().to(torch.float32).contiguous().clone()
+        dev = self.params.device
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.grad = torch.zeros_like(self.params)
+        self.loss = torch.zeros(1, dtype=torch.float32, device=dev)
+        self.ws = torch.empty(lib().pcomp_mlp_workspace_size(max_batch), dtype=torch.uint8, device=dev)
+        self.max_batch, self.lr, self.betas, self.eps, self.step_no = max_batch, lr, betas, eps, 0
+
+    def loss_grad(self, X: torch.Tensor, y: torch.Tensor) -> None:
+        n = X.shape[0]
+        assert 0 < n <= self.max_batch and X.is_contiguous() and y.dtype == torch.uint8
+        rc = lib().pcomp_mlp_loss_grad(_vp(self.params), _vp(X), _vp(y), n, _vp(self.grad), _vp(self.loss),
+                                       _vp(self.ws), self.ws.numel(), _stream_handle())
+        _check(rc, "pcomp_mlp_loss_grad")
+
+    def step(self, X: torch.Tensor, y: torch.Tensor) -> None:
+        self.loss_grad(X, y)
+        self.step_no += 1
+        rc = lib().pcomp_mlp_adam(_vp(self.params), _vp(self.grad), _vp(self.m), _vp(self.v), self.step_no,
+                                  self.lr, self.betas[0], self.betas[1], self.eps, _stream_handle())
+        _check(rc, "pcomp_mlp_adam")

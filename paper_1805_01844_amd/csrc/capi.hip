@@ -12,6 +12,16 @@ int launch_compress_table(const SegDesc *segs, const uint32_t *tile_seg, const S
                           int variant, void *d_out, uint64_t *d_sizes, void *ws, uint32_t grid, hipStream_t st);
 int launch_decompress(const void *d_in, size_t in_size, void *d_out, size_t out_capacity, int32_t *d_status,
                       hipStream_t st);
+int launch_features(const void *d_in, const Layout &lo, float *d_x, uint32_t *d_words, uint8_t *d_label,
+                    void *d_ctx, hipStream_t st);
+int set_model(const float *h, size_t n);
+bool model_loaded();
+uint64_t mlp_ws_bytes(uint64_t n);
+int launch_mlp_scores(const float *prm, const float *X, uint64_t n, float *S, hipStream_t st);
+int launch_mlp_loss_grad(const float *prm, const float *X, const uint8_t *Y, uint64_t n, float *grad, float *loss,
+                         void *ws, hipStream_t st);
+int launch_mlp_adam(float *prm, const float *grad, float *m, float *v, uint32_t step, float lr, float b1, float b2,
+                    float eps, hipStream_t st);
 int launch_decompress_batch(const BatchPlanHeader &ph, const SegDesc *d_segs, const uint32_t *d_tile_seg,
                             const void *d_in, size_t in_size, int32_t *d_status, uint32_t grid, hipStream_t st);
 }  // namespace pcomp
@@ -94,7 +104,7 @@ extern "C" int pcomp_compress(const void *d_in, uint64_t n, pcomp_dtype dtype, u
     const int w = (int)dtype;
     if (!dtype_ok(w) || block_len == 0 || block_len > 65535 || !variant_ok(variant)) return PCOMP_EINVAL;
     if ((uint64_t)block_len * w > kTileBytes) return PCOMP_EINVAL;  // GPU tiles hold whole blocks
-    if (variant == PCOMP_SELECT_LEARNED) return PCOMP_ENOMODEL;
+    if (variant == PCOMP_SELECT_LEARNED && !model_loaded()) return PCOMP_ENOMODEL;
     if ((n && !d_in) || !d_out || !d_out_size || !d_ws) return PCOMP_EINVAL;
     if (((uintptr_t)d_out & 7) || ((uintptr_t)d_ws & 7) || ((uintptr_t)d_in % w)) return PCOMP_EINVAL;
     Layout lo;
@@ -137,7 +147,6 @@ extern "C" int pcomp_batch_plan(const pcomp_segment *h_segs, uint32_t n_segs, co
     uint64_t nt, pb;
     const int rc = batch_shape(h_segs, n_segs, block_len, variant, &nt, &pb);
     if (rc != PCOMP_OK) return rc;
-    if (variant == PCOMP_SELECT_LEARNED) return PCOMP_ENOMODEL;
     if (!h_plan || ((uintptr_t)h_plan & 7)) return PCOMP_EINVAL;
     if (plan_bytes < pb) return PCOMP_ENOSPC;
     BatchPlanHeader *ph = (BatchPlanHeader *)h_plan;
@@ -210,7 +219,7 @@ extern "C" int pcomp_compress_batch(const void *h_plan, const void *d_plan, void
     if (!ph || !d_plan || ((uintptr_t)d_plan & 7)) return PCOMP_EINVAL;
     if ((ph->n_segs && (!d_out || !d_sizes)) || !d_ws || ((uintptr_t)d_out & 7) || ((uintptr_t)d_ws & 7))
         return PCOMP_EINVAL;
-    if (ph->variant == PCOMP_SELECT_LEARNED) return PCOMP_ENOMODEL;
+    if (ph->variant == PCOMP_SELECT_LEARNED && !model_loaded()) return PCOMP_ENOMODEL;
     if (out_capacity < ph->out_bytes) return PCOMP_ENOSPC;
     if (ws_bytes < ph->ws_bytes) return PCOMP_ENOWS;
     if (ph->n_segs == 0) return PCOMP_OK;
@@ -229,4 +238,40 @@ extern "C" int pcomp_decompress_batch(const void *h_plan, const void *d_plan, co
     const SegDesc *segs = (const SegDesc *)((const BatchPlanHeader *)d_plan + 1);
     const uint32_t *tile_seg = (const uint32_t *)(segs + ph->n_segs);
     return launch_decompress_batch(*ph, segs, tile_seg, d_in, in_size, d_status, grid, (hipStream_t)stream);
+}
+
+extern "C" int pcomp_set_model(const float *h_params, size_t n_floats) { return set_model(h_params, n_floats); }
+
+extern "C" int pcomp_block_features(const void *d_in, uint64_t n, pcomp_dtype dtype, uint32_t block_len,
+                                    float *d_x, uint32_t *d_words, uint8_t *d_label, void *d_ws, size_t ws_bytes,
+                                    void *stream) {
+    const int w = (int)dtype;
+    if (!dtype_ok(w) || block_len == 0 || block_len > 65535 || (uint64_t)block_len * w > kTileBytes)
+        return PCOMP_EINVAL;
+    if ((n && !d_in) || !d_ws || ((uintptr_t)d_ws & 7) || ((uintptr_t)d_in % w)) return PCOMP_EINVAL;
+    if (ws_bytes < kCtxBytes) return PCOMP_ENOWS;
+    Layout lo;
+    make_layout(n, w, block_len, 0, lo);
+    return launch_features(d_in, lo, d_x, d_words, d_label, d_ws, (hipStream_t)stream);
+}
+
+extern "C" int pcomp_mlp_scores(const float *d_params, const float *d_x, uint64_t n, float *d_scores, void *stream) {
+    if (n && (!d_params || !d_x || !d_scores)) return PCOMP_EINVAL;
+    return launch_mlp_scores(d_params, d_x, n, d_scores, (hipStream_t)stream);
+}
+
+extern "C" size_t pcomp_mlp_workspace_size(uint64_t n) { return (size_t)mlp_ws_bytes(n); }
+
+extern "C" int pcomp_mlp_loss_grad(const float *d_params, const float *d_x, const uint8_t *d_labels, uint64_t n,
+                                   float *d_grad, float *d_loss, void *d_ws, size_t ws_bytes, void *stream) {
+    if (n == 0 || !d_params || !d_x || !d_labels || !d_grad || !d_ws) return PCOMP_EINVAL;
+    if (n > 0xFFFFFFFFull * 256) return PCOMP_EINVAL;
+    if (ws_bytes < mlp_ws_bytes(n)) return PCOMP_ENOWS;
+    return launch_mlp_loss_grad(d_params, d_x, d_labels, n, d_grad, d_loss, d_ws, (hipStream_t)stream);
+}
+
+extern "C" int pcomp_mlp_adam(float *d_params, const float *d_grad, float *d_m, float *d_v, uint32_t step, float lr,
+                              float beta1, float beta2, float eps, void *stream) {
+    if (!d_params || !d_grad || !d_m || !d_v || step == 0) return PCOMP_EINVAL;
+    return launch_mlp_adam(d_params, d_grad, d_m, d_v, step, lr, beta1, beta2, eps, (hipStream_t)stream);
 }

@@ -22,9 +22,16 @@
 //      the stream header and size.
 // The stats and pack launches are persistent when the caller gives a grid smaller than the
 // tile count: each workgroup then walks the tiles with a stride of the grid.
+#include <atomic>
+
 #include "kernels_common.h"
 
 namespace pcomp {
+
+// Parameters of the learned class selector on this device (pcomp_set_model).
+__constant__ float c_model[kMlpParams];
+constexpr uint32_t kFeatWords = 11;  // per block in LDS: 16 16-bit counts, min, max, L_b
+static_assert(kFeatWords * 4 * kMaxTileBlocks <= kTileBytes, "features must fit in the tile buffer");
 
 struct CompressArgs {
     const SegDesc *segs;        // device table of the batch, or nullptr: the one segment is `one`
@@ -162,6 +169,7 @@ __global__ __launch_bounds__(kThreads) void stats_kernel(CompressArgs a) {
     typedef typename Elem<W>::T V;
     __shared__ uint4 s_raw[kTileBytes / 16 + 1];
     __shared__ uint32_t s_nw[kMaxTileBlocks];
+    __shared__ uint8_t s_pred[kMaxTileBlocks];
     __shared__ uint64_t s_red64[kThreads / 64];
     __shared__ uint32_t s_red32[kThreads / 64];
     __shared__ SizeCtx s_C;
@@ -170,6 +178,7 @@ __global__ __launch_bounds__(kThreads) void stats_kernel(CompressArgs a) {
     const uint32_t tid = threadIdx.x;
     const int variant = a.variant;
     const bool fixed0 = (variant == 0 || variant == 8);
+    const bool learned = variant == PCOMP_SELECT_LEARNED;
     copy_size_ctx(a.ctx, s_C);
     for (uint64_t gt = a.tile_lo + blockIdx.x; gt < a.tile_hi; gt = kPersist ? gt + gridDim.x : a.tile_hi) {
         const SegDesc sd = seg_of(a, gt);
@@ -202,35 +211,67 @@ __global__ __launch_bounds__(kThreads) void stats_kernel(CompressArgs a) {
         // bin b = beta - bitlen(d): digits in octave b below the top; n_e(t) = bins 0 .. t-1
         uint32_t ne_t[8];
         ne_t[0] = 0;
+        Hist16 hist;
         if (!fixed0) {
-            uint64_t h = 0;  // eight 8-bit counters (at most 64 digits per lane)
+            uint64_t lo8 = 0, hi8 = 0;  // 8-bit counters: at most 64 digits per lane
             for (uint32_t j = g; j < Lb; j += G) {
                 const uint32_t b = beta - bitlen32((uint32_t)bv[j] - vmin);
-                h += b < 8 ? (1ull << (8 * b)) : 0;
+                lo8 += b < 8 ? (1ull << (8 * b)) : 0;
+                if (learned) hi8 += b >= 8 ? (1ull << (8 * (b < 15 ? b - 8 : 7))) : 0;
             }
-            uint64_t h0 = 0, h1 = 0;  // widened to 16-bit counters before the group sum
-#pragma unroll
-            for (int t = 0; t < 4; t++) {
-                h0 |= ((h >> (8 * t)) & 0xFF) << (16 * t);
-                h1 |= ((h >> (8 * (t + 4))) & 0xFF) << (16 * t);
+            hist_widen(lo8, hi8, hist);
+            hist.w[0] = group_reduce(hist.w[0], G, AddOp(), s_red64);
+            hist.w[1] = group_reduce(hist.w[1], G, AddOp(), s_red64);
+            if (learned) {
+                hist.w[2] = group_reduce(hist.w[2], G, AddOp(), s_red64);
+                hist.w[3] = group_reduce(hist.w[3], G, AddOp(), s_red64);
             }
-            h0 = group_reduce(h0, G, AddOp(), s_red64);
-            h1 = group_reduce(h1, G, AddOp(), s_red64);
 #pragma unroll
-            for (int t = 1; t < 8; t++)
-                ne_t[t] = ne_t[t - 1] +
-                          (uint32_t)(((t - 1) < 4 ? (h0 >> (16 * (t - 1))) : (h1 >> (16 * (t - 5)))) & 0xFFFF);
+            for (int t = 1; t < 8; t++) ne_t[t] = ne_t[t - 1] + hist_bin(hist, t - 1);
         } else {
 #pragma unroll
             for (int t = 1; t < 8; t++) ne_t[t] = 0;
+        }
+
+        // learned selector: features of every block through LDS (the tile's values are no
+        // longer needed), then one thread per block scores the 16 classes
+        int pred = 0;
+        if (learned) {
+            __syncthreads();
+            uint32_t *s_feat = (uint32_t *)s_raw;  // kFeatWords per block
+            if (live && g == 0) {
+                uint32_t *f = s_feat + blk * kFeatWords;
+#pragma unroll
+                for (int q = 0; q < 4; q++) {
+                    f[2 * q] = (uint32_t)hist.w[q];
+                    f[2 * q + 1] = (uint32_t)(hist.w[q] >> 32);
+                }
+                f[8] = vmin;
+                f[9] = vmax;
+                f[10] = Lb;
+            }
+            __syncthreads();
+            if (tid < nbt) {
+                const uint32_t *f = s_feat + tid * kFeatWords;
+                uint32_t H[16];
+#pragma unroll
+                for (int b = 0; b < 16; b++) H[b] = (f[b >> 1] >> (16 * (b & 1))) & 0xFFFF;
+                float x[kMlpIn], sc[kMlpOut];
+                block_features(H, f[10], f[8], f[9], x);
+                mlp_scores([](int i) { return c_model[i]; }, x, sc);
+                s_pred[tid] = (uint8_t)argmax16(sc);
+            }
+            __syncthreads();
+            pred = live ? s_pred[blk] : 0;
         }
 
         // class choice: lanes of the group split the candidates; argmin, ties to the lowest id
         uint64_t key = ~0ull;
         if (live) {
             for (int c = (int)g; c < 16; c += (int)G) {
-                const bool cand =
-                    fixed0 ? (c == variant) : (c == 0 || variant == PCOMP_SELECT_EXHAUSTIVE || c == variant);
+                const bool cand = fixed0 ? (c == variant)
+                                         : (c == 0 || variant == PCOMP_SELECT_EXHAUSTIVE || c == variant ||
+                                            (learned && c == pred));
                 const int t = c & 7;
                 if (!cand || t > (int)beta) continue;
                 uint32_t nwm, net = 0;
@@ -537,6 +578,133 @@ int launch_compress_table(const SegDesc *segs, const uint32_t *tile_seg, const S
             launch_tiles<4>(false, persist, gg, dyn, b, st);
     }
     return hipGetLastError() == hipSuccess ? PCOMP_OK : PCOMP_EHIP;
+}
+
+// ---- training data: features, class sizes and the exhaustive choice of every block ----
+// One workgroup per tile of one array: per block the 19 selector features, the words of
+// each of the 16 classes (0xFFFFFFFF when invalid) and the class exhaustive search picks
+// (the smallest, ties to the lowest id).
+template <int W>
+__global__ __launch_bounds__(kThreads) void features_kernel(const uint8_t *in, Layout lo, float *fx,
+                                                            uint32_t *words, uint8_t *label, const SizeCtx *ctx,
+                                                            DevTables T) {
+    typedef typename Elem<W>::T V;
+    __shared__ uint4 s_raw[kTileBytes / 16 + 1];
+    __shared__ uint64_t s_red64[kThreads / 64];
+    __shared__ uint32_t s_red32[kThreads / 64];
+    __shared__ SizeCtx s_C;
+    const uint32_t tid = threadIdx.x;
+    const uint64_t tile = blockIdx.x;
+    if (tile >= lo.n_tiles) return;
+    copy_size_ctx(ctx, s_C);
+    const uint32_t L = lo.L, tb = lo.tile_blocks;
+    const uint64_t b0 = tile * tb;
+    const uint32_t nbt = (uint32_t)min((uint64_t)tb, lo.n_blocks - b0);
+    const uint64_t v0 = b0 * L;
+    const uint32_t nvt = (uint32_t)min((uint64_t)nbt * L, lo.n - v0);
+    const V *s_val = stage_tile<W>(in, v0, nvt, s_raw);
+    __syncthreads();
+    const uint32_t G = kThreads / tb;
+    const uint32_t blk = tid / G, g = tid % G;
+    const bool live = blk < nbt;
+    const uint32_t Lb = live ? (uint32_t)min((uint64_t)L, lo.n - (b0 + blk) * L) : 0;
+    const V *bv = s_val + (size_t)blk * L;
+    uint32_t vmin = 0xFFFFFFFFu, vmax = 0;
+    for (uint32_t j = g; j < Lb; j += G) {
+        const uint32_t v = bv[j];
+        vmin = v < vmin ? v : vmin;
+        vmax = v > vmax ? v : vmax;
+    }
+    vmin = group_reduce(vmin, G, MinOp(), s_red32);
+    vmax = group_reduce(vmax, G, MaxOp(), s_red32);
+    const uint64_t B = live ? (uint64_t)vmax - vmin + 1 : 1;
+    const uint32_t beta = bitlen64(B - 1);
+    uint64_t lo8 = 0, hi8 = 0;
+    for (uint32_t j = g; j < Lb; j += G) {
+        const uint32_t b = beta - bitlen32((uint32_t)bv[j] - vmin);
+        lo8 += b < 8 ? (1ull << (8 * b)) : 0;
+        hi8 += b >= 8 ? (1ull << (8 * (b < 15 ? b - 8 : 7))) : 0;
+    }
+    Hist16 hist;
+    hist_widen(lo8, hi8, hist);
+#pragma unroll
+    for (int q = 0; q < 4; q++) hist.w[q] = group_reduce(hist.w[q], G, AddOp(), s_red64);
+    uint32_t ne_t[8];
+    ne_t[0] = 0;
+#pragma unroll
+    for (int t = 1; t < 8; t++) ne_t[t] = ne_t[t - 1] + hist_bin(hist, t - 1);
+    uint64_t key = ~0ull;
+    if (live) {
+        const uint64_t gb = b0 + blk;
+        for (int c = (int)g; c < 16; c += (int)G) {
+            const int t = c & 7;
+            uint32_t nw = 0xFFFFFFFFu;
+            if (t <= (int)beta) {
+                uint32_t nwm, net = 0;
+#pragma unroll
+                for (int tt = 1; tt < 8; tt++) net = (t == tt) ? ne_t[tt] : net;  // no dynamic register index
+                nw = class_words(T, s_C, L, c, Lb, B, beta, net, nwm);
+                const uint64_t k2 = ((uint64_t)nw << 8) | (uint64_t)c;
+                key = k2 < key ? k2 : key;
+            }
+            if (words) words[16 * gb + c] = nw;
+        }
+        if (g == 0 && fx) {
+            uint32_t H[16];
+#pragma unroll
+            for (int b = 0; b < 16; b++) H[b] = hist_bin(hist, b);
+            float x[kMlpIn];
+            block_features(H, Lb, vmin, vmax, x);
+#pragma unroll
+            for (int i = 0; i < kMlpIn; i++) fx[(size_t)kMlpIn * gb + i] = x[i];
+        }
+    }
+    key = group_reduce(key, G, MinOp(), s_red64);
+    if (live && g == 0 && label) label[b0 + blk] = (uint8_t)(key & 0xFF);
+}
+
+__global__ void size_ctx_kernel(SizeCtx *ctx, DevTables T, uint32_t L) { fill_size_ctx(T, L, *ctx); }
+
+int launch_features(const void *d_in, const Layout &lo, float *d_x, uint32_t *d_words, uint8_t *d_label,
+                    void *d_ctx, hipStream_t st) {
+    DevTables T;
+    if (tables_for_current_device(&T) != PCOMP_OK) return PCOMP_EHIP;
+    SizeCtx *ctx = (SizeCtx *)d_ctx;
+    size_ctx_kernel<<<1, kThreads, 0, st>>>(ctx, T, lo.L);
+    if (lo.n_tiles) {
+        const uint32_t grid = (uint32_t)lo.n_tiles;
+        const uint8_t *in = (const uint8_t *)d_in;
+        if (lo.w == 1)
+            features_kernel<1><<<grid, kThreads, 0, st>>>(in, lo, d_x, d_words, d_label, ctx, T);
+        else if (lo.w == 2)
+            features_kernel<2><<<grid, kThreads, 0, st>>>(in, lo, d_x, d_words, d_label, ctx, T);
+        else
+            features_kernel<4><<<grid, kThreads, 0, st>>>(in, lo, d_x, d_words, d_label, ctx, T);
+    }
+    return hipGetLastError() == hipSuccess ? PCOMP_OK : PCOMP_EHIP;
+}
+
+// ---- the selector's parameters, per device -------------------------------------------
+static std::atomic<bool> g_model_loaded[64];
+
+int set_model(const float *h, size_t n) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return PCOMP_EHIP;
+    if (!h) {
+        g_model_loaded[dev] = false;
+        return PCOMP_OK;
+    }
+    if (n != (size_t)kMlpParams) return PCOMP_EINVAL;
+    if (hipMemcpyToSymbol(HIP_SYMBOL(c_model), h, n * sizeof(float), 0, hipMemcpyHostToDevice) != hipSuccess)
+        return PCOMP_EHIP;
+    g_model_loaded[dev] = true;
+    return PCOMP_OK;
+}
+
+bool model_loaded() {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return false;
+    return g_model_loaded[dev];
 }
 
 // A single stream: a table of one segment.

@@ -196,6 +196,86 @@ __device__ inline uint32_t class_words(const DevTables &T, const SizeCtx &C, uin
 }
 
 // ---------------------------------------------------------------------------------------
+// Learned class selector: 19 features of a block -> 64 ReLU units -> 16 class scores.
+// Features use correctly rounded binary32 operations only (so every IEEE implementation
+// gets the same bits): x[b] = H[b] / L_b for the 16-bin octave histogram
+// H[b] = #{j : min(beta - bitlen(d_j), 15) = b}; x[16], x[17] = lg(min + 1) / 32,
+// lg(max + 1) / 32 with the piecewise-linear base-2 logarithm lg(u) = e + (u - 2^e) 2^-e
+// for 2^e <= u < 2^(e+1); x[18] = L_b / 4096. Every sum of the network is a chain of fused
+// multiply-adds in index order starting from the bias. Parameters: W1 (64 x 19,
+// row-major), b1 (64), W2 (16 x 64), b2 (16).
+// ---------------------------------------------------------------------------------------
+constexpr int kMlpIn = 19, kMlpHid = 64, kMlpOut = 16;
+constexpr int kMlpW1 = 0, kMlpB1 = kMlpHid * kMlpIn, kMlpW2 = kMlpB1 + kMlpHid, kMlpB2 = kMlpW2 + kMlpOut * kMlpHid;
+constexpr int kMlpParams = kMlpB2 + kMlpOut;  // 2320
+
+__device__ __forceinline__ float lg_f32(uint64_t u) {  // u >= 1
+    const int e = 63 - __clzll(u);
+    const float frac = ldexpf((float)(uint32_t)(u - (1ull << e)), -e);
+    return (float)e + frac;
+}
+
+// x[0..18] from the histogram (16 counts), L_b and the block's min and max.
+__device__ __forceinline__ void block_features(const uint32_t *H, uint32_t Lb, uint64_t vmin, uint64_t vmax,
+                                               float *x) {
+    const float fl = (float)Lb;
+#pragma unroll
+    for (int b = 0; b < 16; b++) x[b] = (float)H[b] / fl;
+    x[16] = lg_f32(vmin + 1) * 0.03125f;
+    x[17] = lg_f32(vmax + 1) * 0.03125f;
+    x[18] = fl * (1.0f / 4096.0f);
+}
+
+// The 16 scores; P(i) returns parameter i.
+template <typename P>
+__device__ __forceinline__ void mlp_scores(P prm, const float *x, float *s) {
+#pragma unroll
+    for (int k = 0; k < kMlpOut; k++) s[k] = prm(kMlpB2 + k);
+    for (int j = 0; j < kMlpHid; j++) {
+        float a = prm(kMlpB1 + j);
+#pragma unroll
+        for (int i = 0; i < kMlpIn; i++) a = __builtin_fmaf(prm(kMlpW1 + j * kMlpIn + i), x[i], a);
+        a = a > 0.0f ? a : 0.0f;
+#pragma unroll
+        for (int k = 0; k < kMlpOut; k++) s[k] = __builtin_fmaf(prm(kMlpW2 + k * kMlpHid + j), a, s[k]);
+    }
+}
+
+// First index of the largest score.
+__device__ __forceinline__ int argmax16(const float *s) {
+    int best = 0;
+    float bv = s[0];
+#pragma unroll
+    for (int k = 1; k < kMlpOut; k++) {
+        const bool gt = s[k] > bv;
+        best = gt ? k : best;
+        bv = gt ? s[k] : bv;
+    }
+    return best;
+}
+
+// Per-lane octave histogram of digits: bins 0..7 and 8..15 (capped) as eight 8-bit counters
+// each (at most 64 digits per lane), widened to four words of four 16-bit counters.
+struct Hist16 {
+    uint64_t w[4];
+};
+
+__device__ __forceinline__ void hist_widen(uint64_t lo8, uint64_t hi8, Hist16 &h) {
+    h.w[0] = h.w[1] = h.w[2] = h.w[3] = 0;
+#pragma unroll
+    for (int t = 0; t < 4; t++) {
+        h.w[0] |= ((lo8 >> (8 * t)) & 0xFF) << (16 * t);
+        h.w[1] |= ((lo8 >> (8 * (t + 4))) & 0xFF) << (16 * t);
+        h.w[2] |= ((hi8 >> (8 * t)) & 0xFF) << (16 * t);
+        h.w[3] |= ((hi8 >> (8 * (t + 4))) & 0xFF) << (16 * t);
+    }
+}
+
+__device__ __forceinline__ uint32_t hist_bin(const Hist16 &h, int b) {
+    return (uint32_t)(h.w[b >> 2] >> (16 * (b & 3))) & 0xFFFF;
+}
+
+// ---------------------------------------------------------------------------------------
 // Digit arithmetic in 32-bit chunks (see Chunk).
 // ---------------------------------------------------------------------------------------
 __device__ __forceinline__ uint32_t div32_magic(uint32_t x, uint32_t m, uint32_t sh) {
