@@ -34,6 +34,10 @@ def parse():
     ap.add_argument("--block-len", type=int, default=40)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU work of the baseline sample")
+    ap.add_argument("--batch-events", type=int, default=2000,
+                    help="uneven events in the batched leg (0 skips it)")
+    ap.add_argument("--stress-bytes", type=float, default=float(1 << 32),
+                    help="bytes of the stress decompression leg (0 skips it)")
     return ap.parse_args()
 
 
@@ -93,6 +97,104 @@ def cpu_baseline(x_host_events, variant: int, L: int, seconds: float):
             "sample": "%d events cycled from the first %d of the workload (%.1f MB), compress+decompress "
                       "round trip, one stream per event" % (n_ev, len(ev), nbytes / 1e6),
             "ratio": nbytes / sum(sizes)}
+
+
+def _time_pair(comp_fn, dec_fn, reps):
+    """Mean device time (s) of comp_fn and dec_fn over reps, timed with events on the current
+    stream after one untimed call of each."""
+    import torch
+
+    comp_fn()
+    dec_fn()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3 * reps)]
+    for r in range(reps):
+        ev[3 * r].record()
+        comp_fn()
+        ev[3 * r + 1].record()
+        dec_fn()
+        ev[3 * r + 2].record()
+    torch.cuda.synchronize()
+    tc = sum(ev[3 * r].elapsed_time(ev[3 * r + 1]) for r in range(reps)) / reps / 1e3
+    td = sum(ev[3 * r + 1].elapsed_time(ev[3 * r + 2]) for r in range(reps)) / reps / 1e3
+    return tc, td
+
+
+def batch_leg(n_events: int, reps: int):
+    """Uneven camera events (shapes 1855x40, 2048x96, 11328x128; u16 or u32; noise sigma U(2,20);
+    pulse fraction U(0,5%)) as one batch: block lengths and grid from the autotuner, the
+    compression captured in one HIP graph, per-block class by the plain method (class 0), by
+    exhaustive search, and by the shipped learned selector."""
+    import torch
+
+    import datagen
+    import paper_1805_01844_amd as pc
+    from paper_1805_01844_amd import learn, tune
+
+    segs = [e.reshape(-1) for e in datagen.uneven_events(n_events, seed=3, device="cuda")]
+    torch.cuda.synchronize()
+    nbytes = sum(s.numel() * s.element_size() for s in segs)
+    outs = [torch.empty_like(s) for s in segs]
+    learn.use_selector()
+    res = {"workload": "%d uneven camera events, %.3f GB (u16 and u32 mixed)" % (n_events, nbytes / 1e9)}
+    for name, v in (("plain", 0), ("exhaustive", pc.SELECT_EXHAUSTIVE), ("learned", pc.SELECT_LEARNED)):
+        t = tune.autotune(segs, v)
+        b = pc.Batch(segs, block_len=t["block_len"], variant=v, grid=t["grid"])
+        g = b.capture()
+        dec = pc.BatchDecoder(b, outs, grid=t["grid"])
+        tc, td = _time_pair(g.replay, dec, reps)
+        dec.check()
+        ok = all(torch.equal(a.view(torch.uint8), c.view(torch.uint8)) for a, c in zip(segs, outs))
+        assert ok and b.error_flag() == 0, "batched round trip failed (%s)" % name
+        res[name] = {"block_len": list(t["block_len"]), "grid": t["grid"], "ratio": round(nbytes / b.total_bytes(), 4),
+                     "compress_GBps": round(nbytes / tc / 1e9, 1), "decompress_GBps": round(nbytes / td / 1e9, 1),
+                     "roundtrip_bit_exact": True}
+        del g, b, dec
+    pc.set_model(None)
+    ex, le = res["exhaustive"], res["learned"]
+    res["learned_ratio_loss_vs_exhaustive"] = round(1 - le["ratio"] / ex["ratio"], 5)
+    res["learned_ratio_gain_vs_plain"] = round(le["ratio"] / res["plain"]["ratio"] - 1, 5)
+    return res
+
+
+def stress_leg(total_bytes: int, reps: int):
+    """Thirds of u8/u16/u32 stress blocks (Laplacian noise, 0.1% full-range outliers, constant and
+    full-range blocks; L = 1024) plus one u32 block for every base 2..2^16, as one batch; the
+    decompression is the heavy side."""
+    import torch
+
+    import datagen
+    import paper_1805_01844_amd as pc
+
+    L = 1024
+    segs = []
+    for k, dt in enumerate((torch.uint8, torch.uint16, torch.uint32)):
+        w = torch.tensor([], dtype=dt).element_size()
+        nblk = total_bytes // 3 // (L * w)
+        out = torch.empty(nblk * L, dtype=dt, device="cuda")
+        step = (256 << 20) // (L * w)
+        for c, b0 in enumerate(range(0, nblk, step)):
+            nb = min(step, nblk - b0)
+            out[b0 * L:(b0 + nb) * L] = datagen.laplace_blocks(nb, L, dt, seed=90 + 1000 * k + c, device="cuda",
+                                                               outlier_rate=1e-3).reshape(-1)
+        segs.append(out)
+    segs.append(datagen.base_sweep_u32(L=L, device="cuda"))
+    torch.cuda.synchronize()
+    nbytes = sum(s.numel() * s.element_size() for s in segs)
+    outs = [torch.empty_like(s) for s in segs]
+    res = {"workload": "%.3f GB: u8/u16/u32 stress blocks + base sweep 2..65536, L=1024" % (nbytes / 1e9)}
+    for name, v in (("plain", 0), ("exhaustive", pc.SELECT_EXHAUSTIVE)):
+        b = pc.Batch(segs, block_len=L, variant=v)
+        dec = pc.BatchDecoder(b, outs)
+        tc, td = _time_pair(b.compress, dec, reps)
+        dec.check()
+        ok = all(torch.equal(a.view(torch.uint8), c.view(torch.uint8)) for a, c in zip(segs, outs))
+        assert ok and b.error_flag() == 0, "stress round trip failed (%s)" % name
+        res[name] = {"ratio": round(nbytes / b.total_bytes(), 4), "compress_GBps": round(nbytes / tc / 1e9, 1),
+                     "decompress_GBps": round(nbytes / td / 1e9, 1), "roundtrip_bit_exact": True,
+                     "max_stream_offset": max(b.offsets)}
+        del b, dec
+    return res
 
 
 def main():
@@ -196,6 +298,10 @@ def main():
                               "algorithmic_bytes": comp_alg, "ms": round(tc * 1e3, 4),
                               "launches": "prep, stats_kernel, scan_sums_kernel, scan_index_kernel, pack_kernel"},
     }
+    if args.batch_events > 0:
+        res["batched"] = batch_leg(args.batch_events, reps=5)
+    if args.stress_bytes > 0:
+        res["stress"] = stress_leg(int(args.stress_bytes), reps=5)
     if not args.no_cpu:
         xe = x[: min(args.events, 256)].cpu().view(torch.int16).numpy().view(np.uint16)
         res["cpu_baseline"] = cpu_baseline(xe, variant if variant != pc.SELECT_LEARNED else 0x100, L,

@@ -1,0 +1,146 @@
+"""Stress workload on the GPU: 4 GiB of mixed u8/u16/u32 blocks (Laplacian noise with scale
+U(1, 50), 0.1% outliers over the full range, constant and full-range blocks) plus one u32
+block for every base B in [2, 2^16], as one batch whose later streams start past 2^32 bytes.
+Every value round-trips on the GPU; sampled tiles equal the oracle's stream of the same
+blocks byte for byte (block arrays and payload)."""
+import numpy as np
+import pytest
+import torch
+
+import datagen
+
+pytestmark = pytest.mark.gpu
+
+EXH = 0x100
+L = 1024
+
+
+@pytest.fixture(scope="module")
+def pc():
+    import paper_1805_01844_amd as pc
+
+    pc.init()
+    return pc
+
+
+def _as_np(x: torch.Tensor) -> np.ndarray:
+    x = x.cpu().reshape(-1)
+    if x.dtype == torch.uint16:
+        return x.view(torch.int16).numpy().view(np.uint16)
+    if x.dtype == torch.uint32:
+        return x.view(torch.int32).numpy().view(np.uint32)
+    return x.numpy()
+
+
+def stress_segments(total_bytes: int = 1 << 32, seed: int = 90):
+    """Thirds (by bytes) of u8, u16 and u32 stress blocks, generated on the GPU in chunks, then
+    the base sweep."""
+    segs = []
+    for k, dt in enumerate((torch.uint8, torch.uint16, torch.uint32)):
+        w = torch.tensor([], dtype=dt).element_size()
+        nblk = total_bytes // 3 // (L * w)
+        out = torch.empty(nblk * L, dtype=dt, device="cuda")
+        step = (256 << 20) // (L * w)
+        for c, b0 in enumerate(range(0, nblk, step)):
+            nb = min(step, nblk - b0)
+            out[b0 * L:(b0 + nb) * L] = datagen.laplace_blocks(nb, L, dt, seed=seed + 1000 * k + c, device="cuda",
+                                                               outlier_rate=1e-3).reshape(-1)
+        segs.append(out)
+    segs.append(datagen.base_sweep_u32(L=L, device="cuda"))
+    return segs
+
+
+def _parse(buf: np.ndarray):
+    """Header fields and array offsets of a v1 stream (the documented layout)."""
+    h = buf[:64].view(np.uint64)
+    w, flags = int(buf[6]), int(buf[7])
+    Lb, n, nblocks, tb, pw = int(buf[12:16].view(np.uint32)[0]), int(h[2]), int(h[3]), int(h[4]), int(h[5])
+    ntiles = (nblocks + tb - 1) // tb
+    o = 64
+    off = {"index": o}
+    o += 8 * ntiles
+    off["min"] = o
+    o += w * nblocks
+    off["range"] = o
+    o += w * nblocks
+    off["class"] = o
+    if flags & 1:
+        o += nblocks
+    off["ne"] = o
+    neb = 2 if flags & 4 else 1
+    if flags & 2:
+        o += neb * nblocks
+    off["payload"] = (o + 7) & ~7
+    return dict(w=w, flags=flags, L=Lb, n=n, nblocks=nblocks, tb=tb, pw=pw, ntiles=ntiles, neb=neb, off=off)
+
+
+def _tile_parts(buf: np.ndarray, meta: dict, t: int, words_of_tile=None):
+    """Block arrays and payload bytes of tile t."""
+    tb, w, o = meta["tb"], meta["w"], meta["off"]
+    b0, b1 = t * tb, min(meta["nblocks"], (t + 1) * tb)
+    idx = buf[o["index"]:o["index"] + 8 * meta["ntiles"]].view(np.uint64)
+    p0 = int(idx[t])
+    p1 = int(idx[t + 1]) if t + 1 < meta["ntiles"] else meta["pw"]
+    parts = {
+        "min": buf[o["min"] + w * b0:o["min"] + w * b1].tobytes(),
+        "range": buf[o["range"] + w * b0:o["range"] + w * b1].tobytes(),
+        "payload": buf[o["payload"] + 8 * p0:o["payload"] + 8 * p1].tobytes(),
+    }
+    if meta["flags"] & 1:
+        parts["class"] = buf[o["class"] + b0:o["class"] + b1].tobytes()
+    if meta["flags"] & 2:
+        parts["ne"] = buf[o["ne"] + meta["neb"] * b0:o["ne"] + meta["neb"] * b1].tobytes()
+    return parts
+
+
+def test_stress_4gib_batch(pc, orc):
+    segs = stress_segments()
+    raw = sum(s.numel() * s.element_size() for s in segs)
+    print("case: stress batch, %d segments, %.3f GB" % (len(segs), raw / 1e9), flush=True)
+    assert raw >= 1 << 32
+    b = pc.Batch(segs, block_len=L, variant=EXH)
+    assert b.offsets[-1] > 1 << 32  # the base sweep's stream sits past 2^32 bytes
+    b.compress()
+    torch.cuda.synchronize()
+    assert b.error_flag() == 0
+    sizes = b.sizes.tolist()
+    print("ratio %.4f" % (raw / sum(sizes)), flush=True)
+    outs = [torch.empty_like(s) for s in segs]
+    dec = pc.BatchDecoder(b, outs)
+    dec()
+    dec.check()
+    for i, (s, o) in enumerate(zip(segs, outs)):
+        assert torch.equal(s.view(torch.uint8), o.view(torch.uint8)), "segment %d round trip" % i
+    del outs
+    # sampled tiles against the oracle's stream of the same blocks
+    rng = np.random.default_rng(5)
+    for i, s in enumerate(segs):
+        st = b.out[b.offsets[i]:b.offsets[i] + sizes[i]]
+        head = st[:64].cpu().numpy()
+        meta0 = _parse(np.concatenate([head, np.zeros(0, np.uint8)]))
+        nt = meta0["ntiles"]
+        picks = sorted(set([0, nt - 1] + rng.integers(0, nt, 6).tolist()))
+        # the tile index, block arrays and the payload pieces of the sampled tiles
+        host = st.cpu().numpy() if sizes[i] < (256 << 20) else None
+        for t in picks:
+            tb = meta0["tb"]
+            v0, v1 = t * tb * L, min(s.numel(), (t + 1) * tb * L)
+            want = np.frombuffer(orc.compress(_as_np(s[v0:v1]), L, EXH), np.uint8)
+            wm = _parse(want)
+            if host is None:
+                # fetch only what the tile needs: header + index + arrays region + its payload
+                o = meta0["off"]
+                arrays = st[:o["payload"]].cpu().numpy()
+                idx = arrays[o["index"]:o["index"] + 8 * nt].view(np.uint64)
+                p0 = int(idx[t])
+                p1 = int(idx[t + 1]) if t + 1 < nt else meta0["pw"]
+                pay = st[o["payload"] + 8 * p0:o["payload"] + 8 * p1].cpu().numpy()
+                buf = np.zeros(o["payload"] + 8 * p1, np.uint8)
+                buf[:o["payload"]] = arrays
+                buf[o["payload"] + 8 * p0:] = pay
+            else:
+                buf = host
+            got = _tile_parts(buf, _parse(buf), t)
+            ref = _tile_parts(want, wm, 0)
+            assert got == ref, "segment %d tile %d differs from the oracle" % (i, t)
+        print("segment %d: %d tiles sampled" % (i, len(picks)), flush=True)
