@@ -367,6 +367,7 @@ __global__ __launch_bounds__(kThreads) void pack_kernel(CompressArgs a) {
     extern __shared__ uint4 s_dyn[];  // excess lists (kTileBytes) when threshold classes are possible
     __shared__ uint32_t s_min[kMaxTileBlocks], s_rng[kMaxTileBlocks], s_ne[kMaxTileBlocks], s_off[kMaxTileBlocks];
     __shared__ uint8_t s_cls[kMaxTileBlocks];
+    __shared__ uint8_t s_perm[kMaxTileBlocks];  // block packed by lane group p
     __shared__ uint32_t s_red32[kThreads / 64];
     __shared__ SizeCtx s_C;
 
@@ -399,11 +400,22 @@ __global__ __launch_bounds__(kThreads) void pack_kernel(CompressArgs a) {
                                                (lo.flags & kFlagNe16) ? 2 : 1)
                             : 0;
         }
+        // lane groups take the basic blocks first, then the advanced ones (stable), so that
+        // wavefronts mostly run one family's code
+        if (lo.flags & kFlagClass) {
+            const bool adv = tid < nbt && (s_cls[tid] >> 3);
+            uint32_t fam_tot;
+            const uint32_t fam_ex = wg_excl_scan(tid < nbt ? (adv ? 1u << 16 : 1u) : 0u, s_red32, &fam_tot);
+            if (tid < nbt) s_perm[adv ? (fam_tot & 0xFFFF) + (fam_ex >> 16) : (fam_ex & 0xFFFF)] = (uint8_t)tid;
+        } else if (tid < nbt) {
+            s_perm[tid] = (uint8_t)tid;
+        }
         __syncthreads();
 
         const uint32_t G = kThreads / tb;
-        const uint32_t blk = tid / G, g = tid % G;
-        const bool live = blk < nbt;
+        const uint32_t grp = tid / G, g = tid % G;
+        const bool live = grp < nbt;
+        const uint32_t blk = live ? s_perm[grp] : grp;
         const uint32_t Lb = live ? (uint32_t)min((uint64_t)L, lo.n - (b0 + blk) * L) : 0;
         const V *bv = s_val + (size_t)blk * L;
         const uint32_t bmin = live ? s_min[blk] : 0;

@@ -63,6 +63,7 @@ struct DecShared {
     uint32_t min[kMaxTileBlocks], rng[kMaxTileBlocks], ne[kMaxTileBlocks];
     uint32_t nwm[kMaxTileBlocks], off[kMaxTileBlocks + 1];
     uint8_t cls[kMaxTileBlocks];
+    uint8_t perm[kMaxTileBlocks];  // block taken by lane group p: basic blocks first, then advanced
     uint32_t red32[kThreads / 64];
     int bad;
     SizeCtx C;
@@ -194,6 +195,14 @@ __device__ __forceinline__ void decode_tile(const DevTables &T, const uint8_t *i
         const uint32_t ex = wg_excl_scan(nw, S.red32, &tile_words);
         if (tid < nbt) S.off[tid] = ex;
         if (tid == 0) S.off[nbt] = tile_words;
+        // lane groups take the basic blocks first, then the advanced ones (stable), so that
+        // wavefronts mostly run one family's code
+        {
+            const bool adv = tid < nbt && (S.cls[tid] >> 3);
+            uint32_t fam_tot;
+            const uint32_t fam_ex = wg_excl_scan(tid < nbt ? (adv ? 1u << 16 : 1u) : 0u, S.red32, &fam_tot);
+            if (tid < nbt) S.perm[adv ? (fam_tot & 0xFFFF) + (fam_ex >> 16) : (fam_ex & 0xFFFF)] = (uint8_t)tid;
+        }
         __syncthreads();
         if (S.bad || base_off > pw || next_off > pw || next_off != base_off + tile_words) {
             if (tid == 0) set_status(status, PCOMP_ECORRUPT);
@@ -203,8 +212,9 @@ __device__ __forceinline__ void decode_tile(const DevTables &T, const uint8_t *i
         const uint64_t *payload = payload_all + base_off;
 
         // ---- 2. decode: the lanes of a block's group take its words in turn
-        const uint32_t blk = tid / G, g = tid % G;
-        const bool live = blk < nbt;
+        const uint32_t grp = tid / G, g = tid % G;
+        const bool live = grp < nbt;
+        const uint32_t blk = live ? S.perm[grp] : grp;
         if (live) {
             const uint32_t nwb = S.off[blk + 1] - S.off[blk];
             const int c = S.cls[blk];

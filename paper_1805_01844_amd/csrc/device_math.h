@@ -48,6 +48,18 @@ __device__ __forceinline__ uint64_t floor_2p64_div(uint64_t x) {
     return q + (r == x - 1 ? 1 : 0);
 }
 
+// floor(N / d) for N < 2^20 and 1 <= d < 2^24. On the device without an integer divide:
+// (N + 1/2) / d lies at least 1 / (2d) from any integer, and its single-precision product
+// with a reciprocal of at most 1 ulp error is within a relative 2^-22 of it, i.e. within
+// 1 / (4d), so the truncated product is exact.
+__host__ __device__ __forceinline__ uint32_t udiv_small(uint32_t N, uint32_t d) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return (uint32_t)(((float)N + 0.5f) * __builtin_amdgcn_rcpf((float)d));
+#else
+    return N / d;
+#endif
+}
+
 // Index of base B in the precomputed tables, or -1.
 __device__ __forceinline__ int atlas_index(uint64_t B) {
     if (B <= kAtlasDirect) return (int)B;
@@ -123,7 +135,7 @@ __device__ __forceinline__ uint32_t adv_words_slow(const SlowBase sb, uint32_t n
 __host__ __device__ __forceinline__ uint32_t adv_reach(const AtlasEntry *E, const BaseDesc &D, uint32_t t) {
     const uint32_t tot = D.mu + D.lam;
     if (t < tot) return E[t].q + E[t].p;
-    const uint32_t c = (t - D.mu) / D.lam;
+    const uint32_t c = udiv_small(t - D.mu, D.lam);
     const uint32_t r = t - c * D.lam;
     return E[r].q + E[r].p + c * D.V;
 }
@@ -135,8 +147,8 @@ __host__ __device__ __forceinline__ uint32_t adv_reach(const AtlasEntry *E, cons
 __host__ __device__ inline uint32_t adv_words_cycle(const AtlasEntry *E, const BaseDesc &D, uint32_t n) {
     const uint32_t k = D.k;
     if (n <= k) return 1;
-    uint32_t lo = (n + 1 + k) / (k + 1) - 1;  // ceil((n+1)/(k+1)) - 1
-    uint32_t hi = (n + k - 1) / k - 1;        // ceil(n/k) - 1
+    uint32_t lo = udiv_small(n + 1 + k, k + 1) - 1;  // ceil((n+1)/(k+1)) - 1
+    uint32_t hi = udiv_small(n + k - 1, k) - 1;      // ceil(n/k) - 1
     while (lo < hi) {
         const uint32_t mid = (lo + hi) >> 1;
         if (adv_reach(E, D, mid) >= n)
@@ -160,7 +172,7 @@ __device__ __forceinline__ const AtlasEntry *adv_entry(const DevTables &T, const
         q = E[i].q;
         return E + i;
     }
-    uint32_t c = (i - D.mu) / D.lam;
+    uint32_t c = udiv_small(i - D.mu, D.lam);
     uint32_t r = i - c * D.lam;
     q = E[r].q + c * D.V;
     return E + r;
@@ -171,7 +183,7 @@ __device__ inline uint32_t family_words(const DevTables &T, int fam, uint32_t n,
     if (n == 0 || base <= 1) return 0;
     if (!fam) {
         uint32_t k = k_of(T, base);
-        return (n + k - 1) / k;
+        return udiv_small(n + k - 1, k);
     }
     int ai = atlas_index(base);
     if (ai >= 0) return adv_words_atlas(T, T.desc[ai], n);

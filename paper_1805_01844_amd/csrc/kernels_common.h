@@ -155,7 +155,7 @@ __device__ inline void fill_size_ctx(const DevTables &T, uint32_t L, SizeCtx &C)
 // k(B) = max{k : B^k <= 2^64} for B >= 2 (Sec. 3.1 Eq. (1), exact reading), from a float
 // estimate corrected against the exact table.
 __device__ __forceinline__ uint32_t k_fast(const SizeCtx &C, uint64_t B) {
-    uint32_t k = (uint32_t)(64.0f / __log2f((float)B));
+    uint32_t k = (uint32_t)(64.0f * __builtin_amdgcn_rcpf(__log2f((float)B)));  // corrected below
     k = k < 1 ? 1 : (k > 64 ? 64 : k);
     while (k < 64 && B <= C.kmax[k + 1]) k++;
     while (B > C.kmax[k]) k--;
@@ -168,7 +168,7 @@ __device__ inline uint32_t fam_words(const DevTables &T, const SizeCtx &C, int f
                                      uint32_t full) {
     if (n == 0 || base <= 1) return 0;
     const uint32_t k = k_fast(C, base);
-    if (!fam) return (n + k - 1) / k;
+    if (!fam) return udiv_small(n + k - 1, k);
     if (n <= k) return 1;
     const uint64_t bm1 = base - 1;
     if ((bm1 & (bm1 - 1)) == 0 && n == full) return C.p1_adv[bitlen64(bm1) - 1];  // base 2^j + 1
@@ -189,7 +189,7 @@ __device__ inline uint32_t class_words(const DevTables &T, const SizeCtx &C, uin
     const uint32_t j = beta - t;
     const uint64_t Th = 1ull << j;
     if (!fam)
-        nw_main = (Lb + C.p1_k[j] - 1) / C.p1_k[j];
+        nw_main = udiv_small(Lb + C.p1_k[j] - 1, C.p1_k[j]);
     else
         nw_main = (Lb == L) ? C.p1_adv[j] : fam_words(T, C, 1, Lb, Th + 1, L);
     return nw_main + fam_words(T, C, fam, ne_t, B - Th, L);
@@ -324,7 +324,7 @@ __device__ __forceinline__ uint64_t horner_digits(const PartBase &pb, uint32_t l
     }
     const uint32_t B = (uint32_t)pb.base, h = pb.ch.h;
     const uint32_t total = cnt + 1;
-    uint32_t first = total % h;
+    uint32_t first = total - h * udiv_small(total, h);
     if (first == 0) first = h;
     uint32_t s = lead, j = j0;
     for (uint32_t m = 1; m < first; m++) s = __umul24(s, B) + (uint32_t)get(j++);
