@@ -38,6 +38,8 @@ def parse():
                     help="uneven events in the batched leg (0 skips it)")
     ap.add_argument("--stress-bytes", type=float, default=float(1 << 32),
                     help="bytes of the stress decompression leg (0 skips it)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy 1 GiB device to device three times (reference for the HBM byte counters)")
     return ap.parse_args()
 
 
@@ -199,6 +201,18 @@ def stress_leg(total_bytes: int, reps: int):
 
 def main():
     args = parse()
+    if args.copy_calibration:
+        import torch
+
+        a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": 1 << 30, "copies": 3}), flush=True)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build runs on a single MI355X (--gpus 1).", file=sys.stderr)
         sys.exit(2)
@@ -296,7 +310,8 @@ def main():
         "compress_pipeline": {"achieved_GBps": round(comp_alg / tc / 1e9, 1),
                               "frac": round(comp_alg / tc / 1e9 / PEAK_HBM_GBPS, 4),
                               "algorithmic_bytes": comp_alg, "ms": round(tc * 1e3, 4),
-                              "launches": "prep, stats_kernel, scan_sums_kernel, scan_index_kernel, pack_kernel"},
+                              "launches": "prep_kernel, stats_kernel, scan_sums_kernel, scan_prefix_kernel, "
+                                          "pack_kernel"},
     }
     if args.batch_events > 0:
         res["batched"] = batch_leg(args.batch_events, reps=5)

@@ -77,25 +77,33 @@ __device__ void write_header(uint8_t *s, const Layout &lo, int variant, uint64_t
     *size_slot = total;
 }
 
-// Advanced part whose base is outside the tables: one lane walks the series word by word.
+// Advanced part whose base is outside the tables: the state of word i depends on every
+// word before it, so each lane of the group walks the series itself and packs its own
+// words i0, i0 + G, ... (G a power of two).
 template <typename Get>
 __device__ __forceinline__ void pack_adv_slow(const DevTables &T, uint64_t base, uint32_t n, uint32_t nwords,
-                                           uint64_t *dst, Get get) {
+                                              uint32_t i0, uint32_t G, uint64_t *dst, Get get) {
     const SlowBase sb = slow_base(T, base);
-    uint64_t s = 1, rp = 0;
+    uint64_t s = 1, rp = 0;  // carried base R'_{i-1} and top part r'_{i-1} of the split value
     uint32_t q = 0;
     for (uint32_t wi = 0; wi < nwords; wi++) {
         uint32_t p;
         uint64_t R;
-        slow_word(sb, s, p, R);
-        uint64_t acc = rp;
-        for (uint32_t j = 0; j < p; j++) acc = acc * base + get(q + j);
-        const uint64_t x = get(q + p);
-        const uint64_t r = x % R;
-        rp = x / R;
-        dst[wi] = acc * R + r;
+        slow_word_fast(sb, s, p, R);
+        const uint64_t x = get(q + p);  // the value split between this word and the next
+        uint64_t r = x, top = 0;
+        if (R <= x) {
+            top = udiv53(x, R);
+            r = x - top * R;
+        }
+        if (((wi - i0) & (G - 1)) == 0 && wi >= i0) {
+            uint64_t acc = rp;
+            for (uint32_t j = 0; j < p; j++) acc = acc * base + get(q + j);
+            dst[wi] = acc * R + r;
+        }
+        rp = top;
         if (q + p >= n) break;
-        s = (base + R - 1) / R;
+        s = slow_next(sb, R);
         q += p + 1;
     }
 }
@@ -131,8 +139,8 @@ __device__ __forceinline__ void pack_part(const DevTables &T, const SizeCtx &C, 
         }
         return;
     }
-    // base outside the tables: the group's first lane walks the series over the whole part
-    if (i0 == 0) pack_adv_slow(T, base, n, nwords, dst, get);
+    // base outside the tables
+    pack_adv_slow(T, base, n, nwords, i0, G, dst, get);
 }
 
 // Stages the input of one tile in LDS (16-byte chunks; the partial chunks at the ends by
@@ -233,10 +241,43 @@ __global__ __launch_bounds__(kThreads) void stats_kernel(CompressArgs a) {
             for (int t = 1; t < 8; t++) ne_t[t] = 0;
         }
 
-        // learned selector: features of every block through LDS (the tile's values are no
-        // longer needed), then one thread per block scores the 16 classes
+        // learned selector. With at least 4 lanes per block (tile_blocks <= 64) the block's
+        // lanes share its network: hidden units through LDS (the tile's values are no longer
+        // needed), then the scores; otherwise the features go through LDS and one thread per
+        // block scores it. Both keep every sum's order, so the scores are the same bits.
         int pred = 0;
-        if (learned) {
+        if (learned && tb <= kMaxTileBlocks / 4) {
+            __syncthreads();
+            float *s_h = (float *)s_raw;  // [tile_blocks][kMlpHid]
+            if (live) {
+                uint32_t H[16];
+#pragma unroll
+                for (int b = 0; b < 16; b++) H[b] = hist_bin(hist, b);
+                float x[kMlpIn];
+                block_features(H, Lb, vmin, vmax, x);
+                for (uint32_t j = g; j < (uint32_t)kMlpHid; j += G) {
+                    float acc = c_model[kMlpB1 + j];
+#pragma unroll
+                    for (int i = 0; i < kMlpIn; i++) acc = __builtin_fmaf(c_model[kMlpW1 + j * kMlpIn + i], x[i], acc);
+                    s_h[blk * kMlpHid + j] = acc > 0.0f ? acc : 0.0f;
+                }
+            }
+            __syncthreads();
+            uint64_t best = 0;  // (order-preserving score bits, 15 - class): the first top score
+            if (live) {
+                for (uint32_t k = g; k < (uint32_t)kMlpOut; k += G) {
+                    float acc = c_model[kMlpB2 + k];
+                    for (int j = 0; j < kMlpHid; j++)
+                        acc = __builtin_fmaf(c_model[kMlpW2 + k * kMlpHid + j], s_h[blk * kMlpHid + j], acc);
+                    uint32_t u = __float_as_uint(acc == 0.0f ? 0.0f : acc);
+                    u = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+                    const uint64_t key = ((uint64_t)u << 32) | (uint64_t)(15 - k);
+                    best = key > best ? key : best;
+                }
+            }
+            best = group_reduce(best, G, MaxOp(), s_red64);
+            pred = live ? 15 - (int)(best & 0xFF) : 0;
+        } else if (learned) {
             __syncthreads();
             uint32_t *s_feat = (uint32_t *)s_raw;  // kFeatWords per block
             if (live && g == 0) {

@@ -69,37 +69,41 @@ struct DecShared {
     SizeCtx C;
 };
 
-// Advanced part whose base is outside the tables: one lane walks the series word by word
-// (kept out of line: it is rare and register-hungry).
+// Advanced part whose base is outside the tables: each lane of the group walks the series
+// itself (the state of word i depends on every word before it) and decodes its own words
+// i0, i0 + G, ... (G a power of two), including the value split at the end of each.
 template <typename V>
 __device__ __forceinline__ void unpack_adv_slow(const DevTables &T, uint64_t base, uint32_t n, uint32_t nwords,
-                                             const uint64_t *src, V *dst, uint32_t add) {
+                                                uint32_t i0, uint32_t G, const uint64_t *src, V *dst, uint32_t add) {
     const SlowBase sb = slow_base(T, base);
     const Magic mB = magic_dev(base);
-    uint64_t s = 1, r_prev = 0, R_prev = 1;
-    uint32_t q = 0, q_prev = 0, p_prev = 0;
+    uint32_t q = 0, p;
+    uint64_t R;
+    slow_word_fast(sb, 1, p, R);
     for (uint32_t wi = 0; wi < nwords; wi++) {
-        uint32_t p;
-        uint64_t R;
-        slow_word(sb, s, p, R);
-        uint64_t X = src[wi];
-        const uint64_t qR = X / R;
-        const uint64_t r = X - qR * R;
-        X = qR;
-        for (int j = (int)p - 1; j >= 0; j--) {
-            const uint64_t qq = div_magic(X, mB);
-            const uint32_t d = (uint32_t)(X - qq * base);
-            X = qq;
-            if (q + j < n) dst[q + j] = (V)(d + add);
+        const bool last = (q + p >= n) || wi + 1 >= nwords;
+        uint32_t p1 = 0;
+        uint64_t R1 = 1;
+        if (!last) slow_word_fast(sb, slow_next(sb, R), p1, R1);
+        if (((wi - i0) & (G - 1)) == 0 && wi >= i0) {
+            uint64_t r;
+            uint64_t X = udiv64_48(src[wi], R, r);  // word = (r'_{i-1} B^p + digits) R + r
+            for (int j = (int)p - 1; j >= 0; j--) {
+                const uint64_t qq = div_magic(X, mB);
+                if (q + j < n) dst[q + j] = (V)((uint32_t)(X - qq * base) + add);
+                X = qq;
+            }
+            if (!last) {  // r'_i sits on top of the next word, above its p_{i+1} digits
+                uint64_t r1;
+                uint64_t Y = udiv64_48(src[wi + 1], R1, r1);
+                for (uint32_t m = 0; m < p1; m++) Y = div_magic(Y, mB);
+                dst[q + p] = (V)((uint32_t)(Y * R + r) + add);
+            }
         }
-        if (wi > 0 && q_prev + p_prev < n) dst[q_prev + p_prev] = (V)(X * R_prev + r_prev + add);
-        if (q + p >= n) break;
-        r_prev = r;
-        R_prev = R;
-        q_prev = q;
-        p_prev = p;
-        s = (base + R - 1) / R;
+        if (last) break;
         q += p + 1;
+        p = p1;
+        R = R1;
     }
 }
 
@@ -140,8 +144,8 @@ __device__ __forceinline__ void unpack_part(const DevTables &T, const SizeCtx &C
         }
         return;
     }
-    // base outside the tables: the group's first lane walks the series over the whole part
-    if (i0 == 0) unpack_adv_slow<V>(T, base, n, nwords, src, dst, add);
+    // base outside the tables
+    unpack_adv_slow<V>(T, base, n, nwords, i0, G, src, dst, add);
 }
 
 // Decodes tile `tile` of the stream at `in` (layout lo, pw payload words, fixed class of a

@@ -14,6 +14,42 @@ __device__ __forceinline__ uint64_t div_magic(uint64_t x, const Magic &mg) {
     return (t + ((x - t) >> mg.sh1)) >> mg.sh2;
 }
 
+// floor(a / b) for a < 2^53 and 1 <= b < 2^53: the double-precision quotient of the exact
+// operands is within one unit of a / b after truncation, and one integer step corrects it.
+__device__ __forceinline__ uint64_t udiv53(uint64_t a, uint64_t b) {
+    uint64_t q = (uint64_t)((double)a / (double)b);
+    const int64_t r = (int64_t)(a - q * b);
+    if (r < 0)
+        q--;
+    else if ((uint64_t)r >= b)
+        q++;
+    return q;
+}
+
+// floor(X / R) and X mod R for any 64-bit X and 1 <= R < 2^48. The first double quotient
+// is within 2^12 / R + 1 of X / R, so the remainder it leaves is below 2^50 in magnitude
+// and a second quotient plus one unit correction finish exactly.
+__device__ __forceinline__ uint64_t udiv64_48(uint64_t X, uint64_t R, uint64_t &rem) {
+    if (R == 1) {
+        rem = 0;
+        return X;
+    }
+    uint64_t q = (uint64_t)((double)X / (double)R);
+    int64_t r = (int64_t)(X - q * R);
+    const int64_t q1 = (int64_t)floor((double)r / (double)R);
+    r -= q1 * (int64_t)R;
+    q += (uint64_t)q1;
+    if (r < 0) {
+        r += (int64_t)R;
+        q--;
+    } else if ((uint64_t)r >= R) {
+        r -= (int64_t)R;
+        q++;
+    }
+    rem = (uint64_t)r;
+    return q;
+}
+
 // Magic numbers for a divisor d in [1, 2^32], computed on the device: m - 1 =
 // floor((2^l - d) 2^64 / d) by two 64-bit long-division steps on 32-bit limbs
 // (2^l - d < d <= 2^32, so every partial dividend fits 64 bits).
@@ -27,10 +63,9 @@ __device__ inline Magic magic_dev(uint64_t d) {
     }
     uint32_t l = 64 - __clzll(d - 1);
     uint64_t h = (1ull << l) - d;
-    uint64_t n1 = h << 32;
-    uint64_t q1 = n1 / d, r1 = n1 - q1 * d;
-    uint64_t n0 = r1 << 32;
-    uint64_t q0 = n0 / d;
+    uint64_t r1, r0;
+    const uint64_t q1 = udiv64_48(h << 32, d, r1);
+    const uint64_t q0 = udiv64_48(r1 << 32, d, r0);
     mg.m = ((q1 << 32) | q0) + 1;
     mg.sh1 = 1;
     mg.sh2 = l - 1;
@@ -41,12 +76,6 @@ __device__ __forceinline__ Magic magic_dev_outline(uint64_t d) { return magic_de
 
 __device__ __forceinline__ uint32_t bitlen64(uint64_t x) { return x ? 64 - __clzll(x) : 0; }
 __device__ __forceinline__ uint32_t bitlen32(uint32_t x) { return x ? 32 - __clz(x) : 0; }
-
-// floor(2^64 / x) for x >= 2.
-__device__ __forceinline__ uint64_t floor_2p64_div(uint64_t x) {
-    uint64_t q = UINT64_MAX / x, r = UINT64_MAX - q * x;
-    return q + (r == x - 1 ? 1 : 0);
-}
 
 // floor(N / d) for N < 2^20 and 1 <= d < 2^24. On the device without an integer divide:
 // (N + 1/2) / d lies at least 1 / (2d) from any integer, and its single-precision product
@@ -92,41 +121,68 @@ struct SlowBase {
     uint32_t k;
 };
 
+// floor(2^64 / B^p) for p = 1 .. k by a chain of quotients (floor(floor(x / a) / b) =
+// floor(x / (a b))); floor(2^64 / B) < 2^48 for these bases.
 __device__ inline SlowBase slow_base(const DevTables &T, uint64_t B) {
     SlowBase sb;
     sb.B = B;
-    sb.k = k_of(T, B);
-    if (B == (1ull << 32)) {  // B^2 = 2^64 exactly
-        sb.Qk = 1;
-        sb.Qk1 = 1ull << 32;
-        return sb;
+    sb.k = k_of(T, B);  // 2 or 3
+    uint64_t r;
+    uint64_t Q = udiv64_48(UINT64_MAX, B, r);
+    if (r == B - 1) Q++;  // B divides 2^64
+    uint64_t Qprev = Q;
+    for (uint32_t p = 2; p <= sb.k; p++) {
+        Qprev = Q;
+        Q = udiv53(Q, B);
     }
-    uint64_t bk1 = 1;
-    for (uint32_t i = 0; i + 1 < sb.k; i++) bk1 *= B;  // B^(k-1) < 2^64
-    sb.Qk1 = floor_2p64_div(bk1);
-    sb.Qk = floor_2p64_div(bk1 * B);  // B^k < 2^64 here
+    sb.Qk = Q;
+    sb.Qk1 = Qprev;
     return sb;
 }
 
-// One word of the series for a base outside the tables: from the carried base s = R'_{i-1},
-// p_i and R_i (p_i is k when s B^k <= 2^64, else k - 1; R_i = floor(floor(2^64 / B^p) / s)).
-__device__ __forceinline__ void slow_word(const SlowBase &sb, uint64_t s, uint32_t &p, uint64_t &R) {
+// One word of the series for a base outside the tables without integer divides: every
+// floor(2^64 / B^p) is below 2^48 here (B > 2^16 + 1) and the carried base s is at most B.
+__device__ __forceinline__ void slow_word_fast(const SlowBase &sb, uint64_t s, uint32_t &p, uint64_t &R) {
     p = (s <= sb.Qk) ? sb.k : sb.k - 1;
-    R = ((p == sb.k) ? sb.Qk : sb.Qk1) / s;
+    R = udiv53((p == sb.k) ? sb.Qk : sb.Qk1, s);
 }
 
-// Word count of the series (Sec. 3.2) for n digits: walk it word by word.
+// The carried base of the next word, ceil(B / R).
+__device__ __forceinline__ uint64_t slow_next(const SlowBase &sb, uint64_t R) {
+    return R >= sb.B ? 1 : udiv53(sb.B - 1, R) + 1;
+}
+
+// Word count of the series (Sec. 3.2) for n digits: walk it word by word. The carried base
+// s_t determines everything after word t, so once Brent's cycle search finds s_t = s_{t-lam}
+// the series repeats with period lam from there, consuming V = q_t - q_{t-lam} values per
+// period; whole periods are then skipped while they end at or before value n.
 __device__ __forceinline__ uint32_t adv_words_slow(const SlowBase sb, uint32_t n) {
-    uint64_t s = 1;
-    uint32_t q = 0, m = 0;
+    uint64_t s = 1, s_mark = 1;
+    uint32_t q = 0, t = 0, q_mark = 0;
+    uint32_t power = 1, lam = 0;
+    bool skipped = false;
     for (;;) {
         uint32_t p;
         uint64_t R;
-        slow_word(sb, s, p, R);
-        m++;
-        if (q + p >= n) return m;
-        s = (sb.B + R - 1) / R;
+        slow_word_fast(sb, s, p, R);
+        if (q + p >= n) return t + 1;
+        s = slow_next(sb, R);
         q += p + 1;
+        t++;
+        lam++;
+        if (skipped) continue;
+        if (s == s_mark) {
+            const uint32_t V = q - q_mark;
+            const uint32_t c = udiv_small(n - q, V);  // q + c V <= n: no word before is the last
+            q += c * V;
+            t += c * lam;
+            skipped = true;
+        } else if (lam == power) {
+            s_mark = s;
+            q_mark = q;
+            power <<= 1;
+            lam = 0;
+        }
     }
 }
 

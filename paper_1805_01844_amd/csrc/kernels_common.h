@@ -125,6 +125,7 @@ struct MinOp {
 };
 struct MaxOp {
     __device__ uint32_t operator()(uint32_t a, uint32_t b) const { return a > b ? a : b; }
+    __device__ uint64_t operator()(uint64_t a, uint64_t b) const { return a > b ? a : b; }
 };
 struct AddOp {
     __device__ uint64_t operator()(uint64_t a, uint64_t b) const { return a + b; }
