@@ -111,14 +111,14 @@ __device__ __forceinline__ void pack_adv_slow(const DevTables &T, uint64_t base,
 // Packs the words of one part of a block (main digits or the excess list); the lanes of
 // the block's group call it with their first word index and stride. get(j) returns digit j
 // of the part, 0 past its end.
-template <typename Get>
+template <bool Wide, typename Get>
 __device__ __forceinline__ void pack_part(const DevTables &T, const SizeCtx &C, uint64_t base, uint32_t n, int fam,
                                           uint32_t nwords, uint32_t i0, uint32_t G, uint64_t *dst, Get get) {
     if (nwords == 0 || i0 >= nwords) return;
-    const PartBase pb = resolve_base(T, C, base);
+    const PartBase pb = resolve_base<Wide>(T, C, base);
     if (!fam) {
         // Sec. 3.1 Eq. (2): word i holds digits i*k .. i*k+k-1, the first at the highest power
-        for (uint32_t i = i0; i < nwords; i += G) dst[i] = horner_digits(pb, 0, i * pb.k, pb.k, get);
+        for (uint32_t i = i0; i < nwords; i += G) dst[i] = horner_digits<Wide>(pb, 0, i * pb.k, pb.k, get);
         return;
     }
     if (pb.D) {
@@ -135,12 +135,12 @@ __device__ __forceinline__ void pack_part(const DevTables &T, const SizeCtx &C, 
             }
             const uint64_t x = get(q + e->p);
             const uint64_t r = x - div_magic(x, e->mR) * e->R;
-            dst[i] = horner_digits(pb, rp, q, e->p, get) * e->R + r;
+            dst[i] = horner_digits<Wide>(pb, rp, q, e->p, get) * e->R + r;
         }
         return;
     }
-    // base outside the tables
-    pack_adv_slow(T, base, n, nwords, i0, G, dst, get);
+    // base outside the tables (u32 data only)
+    if (Wide) pack_adv_slow(T, base, n, nwords, i0, G, dst, get);
 }
 
 // Stages the input of one tile in LDS (16-byte chunks; the partial chunks at the ends by
@@ -172,7 +172,7 @@ __device__ __forceinline__ void copy_size_ctx(const SizeCtx *g, SizeCtx &s) {
 }
 
 // ---- launch 2: block statistics, class choice, block arrays, tile totals ----------------
-template <int W, bool kPersist>
+template <int W, bool kPersist, bool kLearned>
 __global__ __launch_bounds__(kThreads) void stats_kernel(CompressArgs a) {
     typedef typename Elem<W>::T V;
     __shared__ uint4 s_raw[kTileBytes / 16 + 1];
@@ -186,7 +186,7 @@ __global__ __launch_bounds__(kThreads) void stats_kernel(CompressArgs a) {
     const uint32_t tid = threadIdx.x;
     const int variant = a.variant;
     const bool fixed0 = (variant == 0 || variant == 8);
-    const bool learned = variant == PCOMP_SELECT_LEARNED;
+    const bool learned = kLearned;  // the variant is PCOMP_SELECT_LEARNED
     copy_size_ctx(a.ctx, s_C);
     for (uint64_t gt = a.tile_lo + blockIdx.x; gt < a.tile_hi; gt = kPersist ? gt + gridDim.x : a.tile_hi) {
         const SegDesc sd = seg_of(a, gt);
@@ -318,7 +318,7 @@ __global__ __launch_bounds__(kThreads) void stats_kernel(CompressArgs a) {
                 uint32_t nwm, net = 0;
 #pragma unroll
                 for (int tt = 1; tt < 8; tt++) net = (t == tt) ? ne_t[tt] : net;  // no dynamic register index
-                const uint32_t nw = class_words(T, s_C, L, c, Lb, B, beta, net, nwm);
+                const uint32_t nw = class_words<(W == 4)>(T, s_C, L, c, Lb, B, beta, net, nwm);
                 const uint64_t k2 = ((uint64_t)nw << 8) | (uint64_t)c;
                 key = k2 < key ? k2 : key;
             }
@@ -467,7 +467,7 @@ __global__ __launch_bounds__(kThreads) void pack_kernel(CompressArgs a) {
         const uint32_t ne = live ? s_ne[blk] : 0;
         uint32_t nwm = 0, nw = 0;
         if (live) {
-            nw = class_words(T, s_C, L, cls, Lb, B, beta, ne, nwm);
+            nw = class_words<(W == 4)>(T, s_C, L, cls, Lb, B, beta, ne, nwm);
             const uint32_t per = 8 / W, cap = (Lb + per - 1) / per;
             nw = nw < cap ? nw : cap;
             nwm = nwm < nw ? nwm : nw;
@@ -512,16 +512,16 @@ __global__ __launch_bounds__(kThreads) void pack_kernel(CompressArgs a) {
         if (live && nw) {
             uint64_t *dst = (uint64_t *)(so + lo.off_payload) + base_off + s_off[blk];
             if (tcls == 0) {
-                pack_part(T, s_C, B, Lb, fam, nw, g, G, dst,
+                pack_part<(W == 4)>(T, s_C, B, Lb, fam, nw, g, G, dst,
                           [&](uint32_t j) -> uint64_t { return j < Lb ? (uint64_t)((uint32_t)bv[j] - bmin) : 0; });
             } else {
-                pack_part(T, s_C, Th + 1, Lb, fam, nwm, g, G, dst, [&](uint32_t j) -> uint64_t {
+                pack_part<(W == 4)>(T, s_C, Th + 1, Lb, fam, nwm, g, G, dst, [&](uint32_t j) -> uint64_t {
                     if (j >= Lb) return 0;
                     const uint64_t d = (uint32_t)bv[j] - bmin;
                     return d < Th ? d : Th;
                 });
                 const V *ex = s_exc + (size_t)blk * L;
-                pack_part(T, s_C, B - Th, ne, fam, nw - nwm, g, G, dst + nwm,
+                pack_part<(W == 4)>(T, s_C, B - Th, ne, fam, nw - nwm, g, G, dst + nwm,
                           [&](uint32_t j) -> uint64_t { return j < ne ? (uint64_t)ex[j] : 0; });
             }
         }
@@ -555,14 +555,22 @@ uint64_t compress_ws_bytes(uint64_t n_tiles) {
 // stride, otherwise every workgroup takes one tile (the kernel then holds fewer registers).
 template <int W>
 void launch_tiles(bool stats, bool persist, uint32_t grid, size_t dyn, const CompressArgs &b, hipStream_t st) {
-    if (stats && persist)
-        stats_kernel<W, true><<<grid, kThreads, 0, st>>>(b);
-    else if (stats)
-        stats_kernel<W, false><<<grid, kThreads, 0, st>>>(b);
-    else if (persist)
+    const bool learned = b.variant == PCOMP_SELECT_LEARNED;
+    if (stats && learned) {
+        if (persist)
+            stats_kernel<W, true, true><<<grid, kThreads, 0, st>>>(b);
+        else
+            stats_kernel<W, false, true><<<grid, kThreads, 0, st>>>(b);
+    } else if (stats) {
+        if (persist)
+            stats_kernel<W, true, false><<<grid, kThreads, 0, st>>>(b);
+        else
+            stats_kernel<W, false, false><<<grid, kThreads, 0, st>>>(b);
+    } else if (persist) {
         pack_kernel<W, true><<<grid, kThreads, dyn, st>>>(b);
-    else
+    } else {
         pack_kernel<W, false><<<grid, kThreads, dyn, st>>>(b);
+    }
 }
 
 // Enqueues the four launches for the segments of one table. `one` is used when segs is
@@ -696,7 +704,7 @@ __global__ __launch_bounds__(kThreads) void features_kernel(const uint8_t *in, L
                 uint32_t nwm, net = 0;
 #pragma unroll
                 for (int tt = 1; tt < 8; tt++) net = (t == tt) ? ne_t[tt] : net;  // no dynamic register index
-                nw = class_words(T, s_C, L, c, Lb, B, beta, net, nwm);
+                nw = class_words<(W == 4)>(T, s_C, L, c, Lb, B, beta, net, nwm);
                 const uint64_t k2 = ((uint64_t)nw << 8) | (uint64_t)c;
                 key = k2 < key ? k2 : key;
             }

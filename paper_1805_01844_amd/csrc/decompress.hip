@@ -109,18 +109,18 @@ __device__ __forceinline__ void unpack_adv_slow(const DevTables &T, uint64_t bas
 
 // Decodes words i0, i0+G, ... of one part (main digits or excess list) into dst[0 .. n);
 // `add` is added to every digit (the block minimum for plain blocks).
-template <typename V>
+template <typename V, bool Wide>
 __device__ __forceinline__ void unpack_part(const DevTables &T, const SizeCtx &C, uint64_t base, uint32_t n, int fam,
                                             uint32_t nwords, uint32_t i0, uint32_t G, const uint64_t *src, V *dst,
                                             uint32_t add) {
     if (nwords == 0 || i0 >= nwords) return;
-    const PartBase pb = resolve_base(T, C, base);
+    const PartBase pb = resolve_base<Wide>(T, C, base);
     auto put = [&](uint32_t j, uint32_t d) {
         if (j < n) dst[j] = (V)(d + add);
     };
     if (!fam) {
         // inverse of Sec. 3.1 Eq. (2): the k digits of word i, peeled from the lowest power
-        for (uint32_t i = i0; i < nwords; i += G) peel_digits(pb, src[i], i * pb.k, pb.k, put);
+        for (uint32_t i = i0; i < nwords; i += G) peel_digits<Wide>(pb, src[i], i * pb.k, pb.k, put);
         return;
     }
     if (pb.D) {
@@ -132,7 +132,7 @@ __device__ __forceinline__ void unpack_part(const DevTables &T, const SizeCtx &C
             const uint64_t qR = div_magic(X, e->mR);
             const uint64_t r = X - qR * e->R;  // r_i, the low part of the split value
             const uint32_t p = e->p;
-            peel_digits(pb, qR, q, p, put);  // what remains on top is r'_{i-1}
+            peel_digits<Wide>(pb, qR, q, p, put);  // what remains on top is r'_{i-1}
             // the value split between this word (r_i at the bottom) and the next (r'_i on top)
             if (q + p < n && i + 1 < nwords) {
                 uint32_t q1;
@@ -144,8 +144,8 @@ __device__ __forceinline__ void unpack_part(const DevTables &T, const SizeCtx &C
         }
         return;
     }
-    // base outside the tables
-    unpack_adv_slow<V>(T, base, n, nwords, i0, G, src, dst, add);
+    // base outside the tables (u32 data only)
+    if (Wide) unpack_adv_slow<V>(T, base, n, nwords, i0, G, src, dst, add);
 }
 
 // Decodes tile `tile` of the stream at `in` (layout lo, pw payload words, fixed class of a
@@ -187,7 +187,7 @@ __device__ __forceinline__ void decode_tile(const DevTables &T, const uint8_t *i
             const int t = c & 7;
             const bool ok = c < 16 && t <= (int)beta && ne <= Lb && (t != 0 || ne == 0) && (uint64_t)bmin + rng <= vmaxw;
             uint32_t nwm = 0;
-            if (ok) nw = class_words(T, S.C, L, c, Lb, B, beta, ne, nwm);
+            if (ok) nw = class_words<(W == 4)>(T, S.C, L, c, Lb, B, beta, ne, nwm);
             if (!ok) S.bad = 1;
             S.min[tid] = bmin;
             S.rng[tid] = rng;
@@ -228,12 +228,12 @@ __device__ __forceinline__ void decode_tile(const DevTables &T, const uint8_t *i
             const uint64_t *src = payload + S.off[blk];
             V *vals = s_val + (size_t)blk * L;
             if (t == 0) {
-                unpack_part<V>(T, S.C, B, Lb, fam, nwb, g, G, src, vals, S.min[blk]);
+                unpack_part<V, (W == 4)>(T, S.C, B, Lb, fam, nwb, g, G, src, vals, S.min[blk]);
             } else {
                 const uint64_t Th = 1ull << (bitlen64(B - 1) - t);
                 const uint32_t nwm = S.nwm[blk];
-                unpack_part<V>(T, S.C, Th + 1, Lb, fam, nwm, g, G, src, vals, 0);
-                unpack_part<V>(T, S.C, B - Th, S.ne[blk], fam, nwb - nwm, g, G, src + nwm, s_exc + (size_t)blk * L, 0);
+                unpack_part<V, (W == 4)>(T, S.C, Th + 1, Lb, fam, nwm, g, G, src, vals, 0);
+                unpack_part<V, (W == 4)>(T, S.C, B - Th, S.ne[blk], fam, nwb - nwm, g, G, src + nwm, s_exc + (size_t)blk * L, 0);
             }
         }
         __syncthreads();

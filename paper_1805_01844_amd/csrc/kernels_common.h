@@ -164,7 +164,9 @@ __device__ __forceinline__ uint32_t k_fast(const SizeCtx &C, uint64_t B) {
 }
 
 // Words of family fam (0 basic Sec. 3.1, 1 advanced Sec. 3.2) for n digits of `base`;
-// `full` is the block length L (a block of n == L values can use the cache).
+// `full` is the block length L (a block of n == L values can use the cache). Wide: the data
+// are u32, so a base can lie outside the tables (u8 and u16 bases never do).
+template <bool Wide>
 __device__ inline uint32_t fam_words(const DevTables &T, const SizeCtx &C, int fam, uint32_t n, uint64_t base,
                                      uint32_t full) {
     if (n == 0 || base <= 1) return 0;
@@ -175,16 +177,18 @@ __device__ inline uint32_t fam_words(const DevTables &T, const SizeCtx &C, int f
     if ((bm1 & (bm1 - 1)) == 0 && n == full) return C.p1_adv[bitlen64(bm1) - 1];  // base 2^j + 1
     const int ai = atlas_index(base);
     if (ai >= 0) return adv_words_atlas(T, T.desc[ai], n);
+    if (!Wide) return 0;  // unreachable: every u8 / u16 base is in the tables
     return adv_words_slow(slow_base(T, base), n);
 }
 
 // Words of class c = 8 family + t for a block of Lb digits of base B (beta = bitlen(B-1));
 // ne_t = digits >= T = 2^(beta - t). nw_main receives the main-part words.
+template <bool Wide>
 __device__ inline uint32_t class_words(const DevTables &T, const SizeCtx &C, uint32_t L, int c, uint32_t Lb,
                                        uint64_t B, uint32_t beta, uint32_t ne_t, uint32_t &nw_main) {
     const int fam = c >> 3, t = c & 7;
     if (t == 0) {
-        nw_main = fam_words(T, C, fam, Lb, B, L);
+        nw_main = fam_words<Wide>(T, C, fam, Lb, B, L);
         return nw_main;
     }
     const uint32_t j = beta - t;
@@ -192,8 +196,8 @@ __device__ inline uint32_t class_words(const DevTables &T, const SizeCtx &C, uin
     if (!fam)
         nw_main = udiv_small(Lb + C.p1_k[j] - 1, C.p1_k[j]);
     else
-        nw_main = (Lb == L) ? C.p1_adv[j] : fam_words(T, C, 1, Lb, Th + 1, L);
-    return nw_main + fam_words(T, C, fam, ne_t, B - Th, L);
+        nw_main = (Lb == L) ? C.p1_adv[j] : fam_words<Wide>(T, C, 1, Lb, Th + 1, L);
+    return nw_main + fam_words<Wide>(T, C, fam, ne_t, B - Th, L);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -293,12 +297,13 @@ struct PartBase {
     const BaseDesc *D;    // schedule of the advanced series, nullptr outside the tables
 };
 
+template <bool Wide>
 __device__ __forceinline__ PartBase resolve_base(const DevTables &T, const SizeCtx &C, uint64_t base) {
     PartBase pb;
     pb.base = base;
     const int ai = atlas_index(base);
-    if (ai >= 0) {
-        const BaseDesc &D = T.desc[ai];
+    if (!Wide || ai >= 0) {
+        const BaseDesc &D = T.desc[ai >= 0 ? ai : 2];
         pb.k = D.k;
         pb.ch = D.ch;
         pb.mB = D.mB;
@@ -315,10 +320,10 @@ __device__ __forceinline__ PartBase resolve_base(const DevTables &T, const SizeC
 // Horner over a digit sequence, first digit at the highest power: `lead` then
 // get(j0) .. get(j0 + cnt - 1). Chunks of h digits use 24-bit multiply-adds; the chunks
 // are joined by one 64-bit multiply-add each (the first chunk holds total mod h digits).
-template <typename Get>
+template <bool Wide, typename Get>
 __device__ __forceinline__ uint64_t horner_digits(const PartBase &pb, uint32_t lead, uint32_t j0, uint32_t cnt,
                                                   Get get) {
-    if (pb.ch.h == 0) {
+    if (Wide && pb.ch.h == 0) {  // base >= 2^24 (u32 data only)
         uint64_t acc = lead;
         for (uint32_t j = 0; j < cnt; j++) acc = acc * pb.base + get(j0 + j);
         return acc;
@@ -340,9 +345,9 @@ __device__ __forceinline__ uint64_t horner_digits(const PartBase &pb, uint32_t l
 
 // Peels the lowest cnt base-B digits off X: put(j0 + cnt - 1, lowest digit), ...,
 // put(j0, highest of them); returns what remains above them.
-template <typename Put>
+template <bool Wide, typename Put>
 __device__ __forceinline__ uint64_t peel_digits(const PartBase &pb, uint64_t X, uint32_t j0, uint32_t cnt, Put put) {
-    if (pb.ch.h == 0) {
+    if (Wide && pb.ch.h == 0) {  // base >= 2^24 (u32 data only)
         for (int j = (int)cnt - 1; j >= 0; j--) {
             const uint64_t q = div_magic(X, pb.mB);
             put(j0 + j, (uint32_t)(X - q * pb.base));
