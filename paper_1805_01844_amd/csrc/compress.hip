@@ -31,6 +31,7 @@ namespace pcomp {
 // Parameters of the learned class selector on this device (pcomp_set_model).
 __constant__ float c_model[kMlpParams];
 constexpr uint32_t kFeatWords = 11;  // per block in LDS: 16 16-bit counts, min, max, L_b
+constexpr uint32_t kExcBytes = 2048;  // compaction buffer of a tile's excess lists
 static_assert(kFeatWords * 4 * kMaxTileBlocks <= kTileBytes, "features must fit in the tile buffer");
 
 struct CompressArgs {
@@ -90,23 +91,67 @@ __device__ __forceinline__ void pack_adv_slow(const DevTables &T, uint64_t base,
         uint32_t p;
         uint64_t R;
         slow_word_fast(sb, s, p, R);
+        const bool mine = ((wi - i0) & (G - 1)) == 0 && wi >= i0;
+        uint64_t acc = rp;
+        if (mine)  // digits in increasing order, then the split value
+            for (uint32_t j = 0; j < p; j++) acc = acc * base + get(q + j);
         const uint64_t x = get(q + p);  // the value split between this word and the next
         uint64_t r = x, top = 0;
         if (R <= x) {
             top = udiv53(x, R);
             r = x - top * R;
         }
-        if (((wi - i0) & (G - 1)) == 0 && wi >= i0) {
-            uint64_t acc = rp;
-            for (uint32_t j = 0; j < p; j++) acc = acc * base + get(q + j);
-            dst[wi] = acc * R + r;
-        }
+        if (mine) dst[wi] = acc * R + r;
         rp = top;
         if (q + p >= n) break;
         s = slow_next(sb, R);
         q += p + 1;
     }
 }
+
+// Digits of a threshold block's excess list (d - T for the values d >= T, in data order)
+// read straight from the staged tile, for tiles whose excess lists do not fit the compaction
+// buffer. Lane c of the block's group holds in pre[c] the number of excess values before its
+// chunk of ch values; the digit of rank m lies in the last chunk c with pre[c] <= m. Ranks
+// must be asked in increasing order: consecutive ranks continue the scan inside a chunk, and
+// a chunk left behind is replaced by the one holding the rank.
+template <typename V>
+struct ExcessReader {
+    const V *bv;
+    const uint16_t *pre;
+    uint32_t Lb, ch, G, ne, bmin, Th;
+    uint32_t j, jend, r;  // next position, end of its chunk, rank of the next excess value from j
+    __device__ __forceinline__ void seek(uint32_t m) {
+        uint32_t lo = 0, hi = G - 1;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi + 1) >> 1;
+            if (pre[mid] <= m)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        j = lo * ch;
+        jend = j + ch < Lb ? j + ch : Lb;
+        r = pre[lo];
+    }
+    __device__ __forceinline__ uint64_t operator()(uint32_t m) {
+        if (m >= ne) return 0;
+        bool sought = m != r || j >= jend;
+        if (sought) seek(m);
+        for (;;) {
+            for (; j < jend; j++) {
+                const uint32_t d = (uint32_t)bv[j] - bmin;
+                if (d >= Th && r++ == m) {
+                    j++;
+                    return d - Th;
+                }
+            }
+            if (sought) return 0;  // not reached: the chunk holding rank m was found from the counts
+            seek(m);  // the rest of this chunk held no excess value
+            sought = true;
+        }
+    }
+};
 
 // Packs the words of one part of a block (main digits or the excess list); the lanes of
 // the block's group call it with their first word index and stride. get(j) returns digit j
@@ -133,9 +178,11 @@ __device__ __forceinline__ void pack_part(const DevTables &T, const SizeCtx &C, 
                 const AtlasEntry *ep = adv_entry(T, D, i - 1, qp);
                 rp = (uint32_t)div_magic(get(q - 1), ep->mR);
             }
+            // digits are read in increasing order (the excess-list reader relies on it)
+            const uint64_t acc = horner_digits<Wide>(pb, rp, q, e->p, get);
             const uint64_t x = get(q + e->p);
             const uint64_t r = x - div_magic(x, e->mR) * e->R;
-            dst[i] = horner_digits<Wide>(pb, rp, q, e->p, get) * e->R + r;
+            dst[i] = acc * e->R + r;
         }
         return;
     }
@@ -405,8 +452,12 @@ template <int W, bool kPersist>
 __global__ __launch_bounds__(kThreads) void pack_kernel(CompressArgs a) {
     typedef typename Elem<W>::T V;
     __shared__ uint4 s_raw[kTileBytes / 16 + 1];
-    extern __shared__ uint4 s_dyn[];  // excess lists (kTileBytes) when threshold classes are possible
-    __shared__ uint32_t s_min[kMaxTileBlocks], s_rng[kMaxTileBlocks], s_ne[kMaxTileBlocks], s_off[kMaxTileBlocks];
+    __shared__ uint16_t s_cpre[kThreads];  // threshold blocks: excess values before each lane's chunk
+    __shared__ uint4 s_exc[kExcBytes / 16];  // compacted excess lists of the tile, when they fit
+    __shared__ uint16_t s_exoff[kMaxTileBlocks];
+    __shared__ uint32_t s_extot;
+    __shared__ V s_min[kMaxTileBlocks], s_rng[kMaxTileBlocks];  // at the element width
+    __shared__ uint16_t s_ne[kMaxTileBlocks], s_off[kMaxTileBlocks];  // a tile holds at most 2304 words
     __shared__ uint8_t s_cls[kMaxTileBlocks];
     __shared__ uint8_t s_perm[kMaxTileBlocks];  // block packed by lane group p
     __shared__ uint32_t s_red32[kThreads / 64];
@@ -433,13 +484,21 @@ __global__ __launch_bounds__(kThreads) void pack_kernel(CompressArgs a) {
         // the tile's block arrays, as the statistics launch wrote them
         if (tid < nbt) {
             const uint64_t gb = b0 + tid;
-            s_min[tid] = (uint32_t)get_le(so + lo.off_min + gb * W, W);
-            s_rng[tid] = (uint32_t)get_le(so + lo.off_range + gb * W, W);
+            s_min[tid] = (V)get_le(so + lo.off_min + gb * W, W);
+            s_rng[tid] = (V)get_le(so + lo.off_range + gb * W, W);
             s_cls[tid] = (lo.flags & kFlagClass) ? so[lo.off_class + gb] : (uint8_t)variant;
             s_ne[tid] = (lo.flags & kFlagNe)
-                            ? (uint32_t)get_le(so + lo.off_ne + gb * ((lo.flags & kFlagNe16) ? 2 : 1),
+                            ? (uint16_t)get_le(so + lo.off_ne + gb * ((lo.flags & kFlagNe16) ? 2 : 1),
                                                (lo.flags & kFlagNe16) ? 2 : 1)
-                            : 0;
+                            : (uint16_t)0;
+        }
+        // excess lists of the tile's threshold blocks: their places in the compaction buffer
+        if (!fixed0) {
+            const uint32_t mine = (tid < nbt && (s_cls[tid] & 7)) ? s_ne[tid] : 0;
+            uint32_t tot;
+            const uint32_t off = wg_excl_scan(mine, s_red32, &tot);
+            if (tid < nbt) s_exoff[tid] = (uint16_t)off;
+            if (tid == 0) s_extot = tot;
         }
         // lane groups take the basic blocks first, then the advanced ones (stable), so that
         // wavefronts mostly run one family's code
@@ -472,19 +531,22 @@ __global__ __launch_bounds__(kThreads) void pack_kernel(CompressArgs a) {
             nw = nw < cap ? nw : cap;
             nwm = nwm < nw ? nwm : nw;
         }
-        if (live && g == 0) s_off[blk] = nw;
+        if (live && g == 0) s_off[blk] = (uint16_t)nw;
         const uint64_t Th = tcls ? (1ull << (beta - tcls)) : 0;
-        // excess lists of threshold blocks, in data order (chunked per lane)
-        V *s_exc = (V *)s_dyn;
+        // threshold blocks: count the excess values (d >= T) of every lane's chunk and, when the
+        // tile's lists fit the buffer, compact them there in data order
+        const uint32_t ch = (Lb + G - 1) / G;
+        const bool compact = !fixed0 && s_extot * W <= kExcBytes;
+        V *s_ex = (V *)s_exc;
         if (!fixed0) {
-            const uint32_t ch = (Lb + G - 1) / G;
             const uint32_t j0 = g * ch < Lb ? g * ch : Lb, j1 = (g + 1) * ch < Lb ? (g + 1) * ch : Lb;
             uint32_t cnt = 0;
             if (tcls)
                 for (uint32_t j = j0; j < j1; j++) cnt += ((uint32_t)bv[j] - bmin) >= Th;
             uint32_t pos = group_excl_scan(cnt, G, s_red32);
-            if (tcls) {
-                V *ex = s_exc + (size_t)blk * L;
+            s_cpre[tid] = (uint16_t)pos;
+            if (tcls && compact) {
+                V *ex = s_ex + (live ? s_exoff[blk] : 0);
                 for (uint32_t j = j0; j < j1; j++) {
                     const uint32_t d = (uint32_t)bv[j] - bmin;
                     if (d >= Th && pos < ne) ex[pos++] = (V)(d - Th);
@@ -495,7 +557,7 @@ __global__ __launch_bounds__(kThreads) void pack_kernel(CompressArgs a) {
         uint32_t total;
         const uint32_t my = tid < nbt ? s_off[tid] : 0;
         const uint32_t ex_off = wg_excl_scan(my, s_red32, &total);
-        if (tid < nbt) s_off[tid] = ex_off;
+        if (tid < nbt) s_off[tid] = (uint16_t)ex_off;
         __syncthreads();
 
         // the offset is checked against the bound before anything is written at it
@@ -520,9 +582,15 @@ __global__ __launch_bounds__(kThreads) void pack_kernel(CompressArgs a) {
                     const uint64_t d = (uint32_t)bv[j] - bmin;
                     return d < Th ? d : Th;
                 });
-                const V *ex = s_exc + (size_t)blk * L;
-                pack_part<(W == 4)>(T, s_C, B - Th, ne, fam, nw - nwm, g, G, dst + nwm,
-                          [&](uint32_t j) -> uint64_t { return j < ne ? (uint64_t)ex[j] : 0; });
+                if (compact) {
+                    const V *ex = s_ex + s_exoff[blk];
+                    pack_part<(W == 4)>(T, s_C, B - Th, ne, fam, nw - nwm, g, G, dst + nwm,
+                                        [&](uint32_t j) -> uint64_t { return j < ne ? (uint64_t)ex[j] : 0; });
+                } else {
+                    ExcessReader<V> exr{bv, s_cpre + (tid - g), Lb, ch, G, ne, bmin, (uint32_t)Th, 0, 0, 0};
+                    pack_part<(W == 4)>(T, s_C, B - Th, ne, fam, nw - nwm, g, G, dst + nwm,
+                                        [&](uint32_t j) -> uint64_t { return exr(j); });
+                }
             }
         }
         __syncthreads();  // LDS is reused by the next tile
@@ -600,7 +668,7 @@ int launch_compress_table(const SegDesc *segs, const uint32_t *tile_seg, const S
     a.tile_hi = 0;
     a.ctx = ctx;
     prep_kernel<<<1, kThreads, 0, st>>>(a, ctx, L[0], L[1], L[2], n_segs);
-    const size_t dyn = (variant == 0 || variant == 8) ? 0 : kTileBytes;
+    const size_t dyn = 0;
     for (int g = 0; g < 3; g++) {
         const uint64_t ntg = tile_hi[g] - tile_lo[g];
         if (!ntg) continue;

@@ -138,3 +138,14 @@ def test_corrupt_stream_sets_status(pc, orc):
     assert int(st.item()) == pc.ECORRUPT
     pc.decompress_into(torch.from_numpy(want).cuda(), out[: n // 2], st)
     assert int(st.item()) == pc.ENOSPC
+
+
+@pytest.mark.parametrize("variant", [6, 7, 14, 15, EXH])
+def test_dense_excess_lists(pc, orc, variant):
+    """Near-uniform data with high thresholds: most values are excess, so a tile's excess lists
+    overflow the compaction buffer and packing reads them straight from the tile."""
+    g = torch.Generator().manual_seed(77)
+    for dt, hi, L in [(torch.uint16, 1 << 16, 1024), (torch.uint8, 256, 2048), (torch.uint32, 1 << 20, 512)]:
+        x = torch.randint(0, hi, (7 * L + 13,), generator=g, dtype=torch.int64)
+        x = x.to(torch.int32).to(dt) if dt != torch.uint8 else x.to(dt)
+        _check(pc, orc, x, L, variant, "dense_excess")
