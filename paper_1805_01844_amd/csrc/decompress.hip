@@ -57,9 +57,13 @@ __device__ bool read_layout(const uint8_t *in, uint64_t in_size, Layout &lo, uin
     return true;
 }
 
+constexpr uint32_t kDecExcBytes = 8192;
+
 struct DecShared {
     uint4 raw[kTileBytes / 16];  // decoded digits / values of the tile
-    uint4 exc[kTileBytes / 16];  // decoded excess lists
+    uint4 exc[kDecExcBytes / 16];  // decoded excess lists of the tile, when they fit
+    uint16_t exoff[kMaxTileBlocks];  // each threshold block's place among the tile's excess values
+    uint32_t extot;
     uint32_t min[kMaxTileBlocks], rng[kMaxTileBlocks], ne[kMaxTileBlocks];
     uint32_t nwm[kMaxTileBlocks], off[kMaxTileBlocks + 1];
     uint8_t cls[kMaxTileBlocks];
@@ -161,7 +165,6 @@ __device__ __forceinline__ void decode_tile(const DevTables &T, const uint8_t *i
     const uint64_t *payload_all = (const uint64_t *)(in + lo.off_payload);
     const uint64_t vmaxw = (1ull << (8 * W)) - 1;
     V *s_val = (V *)S.raw;
-    V *s_exc = (V *)S.exc;
     const int neb = (lo.flags & kFlagNe16) ? 2 : 1;
     {
         const uint64_t b0 = tile * tb;
@@ -195,6 +198,14 @@ __device__ __forceinline__ void decode_tile(const DevTables &T, const uint8_t *i
             S.ne[tid] = ne;
             S.nwm[tid] = nwm;
         }
+        // excess lists of the tile's threshold blocks: their places in the decoded excess buffer
+        {
+            const uint32_t mine = (tid < nbt && (S.cls[tid] & 7)) ? S.ne[tid] : 0;
+            uint32_t tot;
+            const uint32_t off = wg_excl_scan(mine, S.red32, &tot);
+            if (tid < nbt) S.exoff[tid] = (uint16_t)off;
+            if (tid == 0) S.extot = tot;
+        }
         uint32_t tile_words;
         const uint32_t ex = wg_excl_scan(nw, S.red32, &tile_words);
         if (tid < nbt) S.off[tid] = ex;
@@ -214,6 +225,9 @@ __device__ __forceinline__ void decode_tile(const DevTables &T, const uint8_t *i
             return;
         }
         const uint64_t *payload = payload_all + base_off;
+        // decoded excess digits go to LDS when they fit, else to the tile's own output range,
+        // which nothing reads or writes until the final store of the tile
+        V *s_exc = S.extot * W <= kDecExcBytes ? (V *)S.exc : (V *)(out + v0 * W);
 
         // ---- 2. decode: the lanes of a block's group take its words in turn
         const uint32_t grp = tid / G, g = tid % G;
@@ -233,7 +247,7 @@ __device__ __forceinline__ void decode_tile(const DevTables &T, const uint8_t *i
                 const uint64_t Th = 1ull << (bitlen64(B - 1) - t);
                 const uint32_t nwm = S.nwm[blk];
                 unpack_part<V, (W == 4)>(T, S.C, Th + 1, Lb, fam, nwm, g, G, src, vals, 0);
-                unpack_part<V, (W == 4)>(T, S.C, B - Th, S.ne[blk], fam, nwb - nwm, g, G, src + nwm, s_exc + (size_t)blk * L, 0);
+                unpack_part<V, (W == 4)>(T, S.C, B - Th, S.ne[blk], fam, nwb - nwm, g, G, src + nwm, s_exc + S.exoff[blk], 0);
             }
         }
         __syncthreads();
@@ -262,7 +276,7 @@ __device__ __forceinline__ void decode_tile(const DevTables &T, const uint8_t *i
                 const uint32_t ne = S.ne[blk];
                 const uint32_t bmin = S.min[blk];
                 const bool exc_words = (uint64_t)S.rng[blk] + 1 - Tb > 1;  // else every excess is 0
-                const V *ex = s_exc + (size_t)blk * L;
+                const V *ex = s_exc + S.exoff[blk];
                 for (uint32_t j = j0; j < j1; j++) {
                     uint32_t d = vals[j];
                     if (d == Tb) {
@@ -302,8 +316,11 @@ __device__ __forceinline__ void decode_tile(const DevTables &T, const uint8_t *i
 
 // One kernel per element width (the stream's width is only known on the device): each
 // returns at once unless the header carries its width, so only one does the work.
+// Five wavefronts per SIMD (at most 96 vector registers) fit without spilling for u8 and u16,
+// and five workgroups per CU fit the LDS (under 32 KiB each, with the 8 KiB excess buffer).
 template <int W>
-__global__ __launch_bounds__(kThreads) void decompress_kernel(DecompressArgs a) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(W == 4 ? 4 : 5))) void decompress_kernel(
+    DecompressArgs a) {
     __shared__ DecShared S;
     Layout lo;
     uint64_t pw;
@@ -331,7 +348,8 @@ __global__ __launch_bounds__(kThreads) void decompress_kernel(DecompressArgs a) 
 // Batch: the tiles of one width group, each decoded into its segment's destination. A
 // segment whose stream header disagrees with the plan is reported corrupt and skipped.
 template <int W>
-__global__ __launch_bounds__(kThreads) void decompress_batch_kernel(BatchDecArgs a) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(W == 4 ? 4 : 5))) void decompress_batch_kernel(
+    BatchDecArgs a) {
     __shared__ DecShared S;
     fill_size_ctx(a.T, a.L, S.C);
     __syncthreads();
