@@ -353,9 +353,31 @@ __global__ __launch_bounds__(kThreads) void stats_kernel(CompressArgs a) {
             pred = live ? s_pred[blk] : 0;
         }
 
-        // class choice: lanes of the group split the candidates; argmin, ties to the lowest id
+        // class choice: lanes of the group split the candidates; argmin, ties to the lowest id.
+        // Exhaustive search sizes classes 0 and 8 on every lane first; a threshold class is then
+        // sized only if its main part (plus one word for a non-empty excess list) could still
+        // beat the best (words, id) key seen by the lane, so the classes it skips cannot win.
         uint64_t key = ~0ull;
-        if (live) {
+        if (live && variant == PCOMP_SELECT_EXHAUSTIVE) {
+            uint32_t nwm;
+            key = (uint64_t)class_words<(W == 4)>(T, s_C, L, 0, Lb, B, beta, 0, nwm) << 8;
+            if (beta >= 1) {
+                const uint64_t k8 = ((uint64_t)class_words<(W == 4)>(T, s_C, L, 8, Lb, B, beta, 0, nwm) << 8) | 8;
+                key = k8 < key ? k8 : key;
+            }
+            for (int c = (int)g; c < 16; c += (int)G) {
+                const int t = c & 7;
+                if (t == 0 || t > (int)beta) continue;
+                uint32_t net = 0;
+#pragma unroll
+                for (int tt = 1; tt < 8; tt++) net = (t == tt) ? ne_t[tt] : net;  // no dynamic register index
+                const uint32_t lb = main_words<(W == 4)>(T, s_C, L, c >> 3, t, Lb, beta) + (net ? 1 : 0);
+                if ((((uint64_t)lb << 8) | (uint64_t)c) >= key) continue;
+                const uint32_t nw = class_words<(W == 4)>(T, s_C, L, c, Lb, B, beta, net, nwm);
+                const uint64_t k2 = ((uint64_t)nw << 8) | (uint64_t)c;
+                key = k2 < key ? k2 : key;
+            }
+        } else if (live) {
             for (int c = (int)g; c < 16; c += (int)G) {
                 const bool cand = fixed0 ? (c == variant)
                                          : (c == 0 || variant == PCOMP_SELECT_EXHAUSTIVE || c == variant ||

@@ -157,9 +157,15 @@ __device__ inline void fill_size_ctx(const DevTables &T, uint32_t L, SizeCtx &C)
 // estimate corrected against the exact table.
 __device__ __forceinline__ uint32_t k_fast(const SizeCtx &C, uint64_t B) {
     uint32_t k = (uint32_t)(64.0f * __builtin_amdgcn_rcpf(__log2f((float)B)));  // corrected below
-    k = k < 1 ? 1 : (k > 64 ? 64 : k);
-    while (k < 64 && B <= C.kmax[k + 1]) k++;
-    while (B > C.kmax[k]) k--;
+    k = k < 1 ? 1 : (k > 63 ? 63 : k);
+    const uint64_t cur = C.kmax[k], up = C.kmax[k + 1];  // both bounds fetched together
+    if (B <= up) {
+        k++;
+        while (k < 64 && B <= C.kmax[k + 1]) k++;
+    } else if (B > cur) {
+        k--;
+        while (B > C.kmax[k]) k--;
+    }
     return k;
 }
 
@@ -179,6 +185,16 @@ __device__ inline uint32_t fam_words(const DevTables &T, const SizeCtx &C, int f
     if (ai >= 0) return adv_words_atlas(T, T.desc[ai], n);
     if (!Wide) return 0;  // unreachable: every u8 / u16 base is in the tables
     return adv_words_slow(slow_base(T, base), n);
+}
+
+// Words of the main part (digits min(d, T) in base T + 1, T = 2^(beta - t)) of a threshold
+// class, t >= 1: a lower bound of the class's words.
+template <bool Wide>
+__device__ __forceinline__ uint32_t main_words(const DevTables &T, const SizeCtx &C, uint32_t L, int fam, int t,
+                                               uint32_t Lb, uint32_t beta) {
+    const uint32_t j = beta - t;
+    if (!fam) return udiv_small(Lb + C.p1_k[j] - 1, C.p1_k[j]);
+    return (Lb == L) ? C.p1_adv[j] : fam_words<Wide>(T, C, 1, Lb, (1ull << j) + 1, L);
 }
 
 // Words of class c = 8 family + t for a block of Lb digits of base B (beta = bitlen(B-1));
