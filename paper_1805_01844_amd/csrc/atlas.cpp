@@ -55,10 +55,7 @@ Chunk chunk_host(uint64_t B) {
     c.h = h;
     c.P = (uint32_t)P;
     c.mP = magic_host(P);
-    uint32_t l = 0;
-    while ((1ull << l) < B) l++;
-    c.m32 = (uint32_t)((((1ull << l) - B) << 32) / B) + 1;
-    c.sh32 = l - 1;
+    c.rB = 1.0 / (double)B;  // IEEE division: correctly rounded
     return c;
 }
 

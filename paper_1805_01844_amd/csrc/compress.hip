@@ -32,6 +32,7 @@ namespace pcomp {
 __constant__ float c_model[kMlpParams];
 constexpr uint32_t kFeatWords = 11;  // per block in LDS: 16 16-bit counts, min, max, L_b
 constexpr uint32_t kExcBytes = 2048;  // compaction buffer of a tile's excess lists
+constexpr uint32_t kAdvTab = kAtlasDirect + 1;  // entries of an advanced-count table (bases 0 .. 2^16 + 1)
 static_assert(kFeatWords * 4 * kMaxTileBlocks <= kTileBytes, "features must fit in the tile buffer");
 
 struct CompressArgs {
@@ -215,6 +216,7 @@ __device__ __forceinline__ const typename Elem<W>::T *stage_tile(const uint8_t *
 }
 
 __device__ __forceinline__ void copy_size_ctx(const SizeCtx *g, SizeCtx &s) {
+    static_assert(sizeof(SizeCtx) / 4 <= kThreads, "one word per thread");
     if (threadIdx.x < sizeof(SizeCtx) / 4) ((uint32_t *)&s)[threadIdx.x] = ((const uint32_t *)g)[threadIdx.x];
 }
 
@@ -623,10 +625,10 @@ __global__ __launch_bounds__(kThreads) void pack_kernel(CompressArgs a) {
 // Clears the error word, fills the size tables of the three width groups (block length L[g])
 // and writes the header of every segment without values (its stream has no tiles).
 __global__ __launch_bounds__(kThreads) void prep_kernel(CompressArgs a, SizeCtx *ctx, uint32_t L0, uint32_t L1,
-                                                         uint32_t L2, uint32_t n_segs) {
+                                                         uint32_t L2, uint32_t n_segs, const uint16_t *adv_tab) {
     const uint32_t Ls[3] = {L0, L1, L2};
     for (int g = 0; g < 3; g++)
-        if (Ls[g]) fill_size_ctx(a.T, Ls[g], ctx[g]);
+        if (Ls[g]) fill_size_ctx(a.T, Ls[g], ctx[g], adv_tab ? adv_tab + (size_t)g * kAdvTab : nullptr);
     if (threadIdx.x == 0) *a.err = 0;
     for (uint32_t s = threadIdx.x; s < n_segs; s += kThreads) {
         const SegDesc sd = a.segs ? a.segs[s] : a.one;
@@ -634,11 +636,23 @@ __global__ __launch_bounds__(kThreads) void prep_kernel(CompressArgs a, SizeCtx 
     }
 }
 
-// Workspace: [err u32, 0 u32][3 size tables, kCtxBytes each][one u32 word total per tile,
-// padded to 8 bytes][one u64 prefix per tile][one u64 sum per run of kScanTiles tiles].
+// Advanced word counts of a full block (L digits) for every base B <= 2^16 + 1, per call and
+// width group: the statistics and packing launches read them instead of searching the
+// series of each block.
+__global__ __launch_bounds__(kThreads) void adv_table_kernel(DevTables T, uint32_t L, uint16_t *tab) {
+    const uint32_t B = blockIdx.x * kThreads + threadIdx.x;
+    if (B >= kAdvTab) return;
+    tab[B] = B < 2 ? 0 : (uint16_t)adv_words_atlas(T, T.desc[B], L);
+}
+
+// Workspace: [err u32, 0 u32][3 size tables, kCtxBytes each][3 advanced-count tables of
+// kAdvTab u16, padded to 8 bytes][one u32 word total per tile, padded to 8 bytes][one u64
+// prefix per tile][one u64 sum per run of kScanTiles tiles].
+constexpr uint64_t kAdvTabBytes = 3 * ((2ull * kAdvTab + 7) & ~7ull);
 uint64_t compress_ws_bytes(uint64_t n_tiles) {
     const uint64_t nt = n_tiles ? n_tiles : 1;
-    return 8 + 3 * kCtxBytes + 4 * ((nt + 1) & ~1ull) + 8 * nt + 8 * ((nt + kScanTiles - 1) / kScanTiles);
+    return 8 + 3 * kCtxBytes + kAdvTabBytes + 4 * ((nt + 1) & ~1ull) + 8 * nt +
+           8 * ((nt + kScanTiles - 1) / kScanTiles);
 }
 
 // One per-tile launch (stats or pack) of width W; a persistent grid walks the tiles with a
@@ -680,16 +694,23 @@ int launch_compress_table(const SegDesc *segs, const uint32_t *tile_seg, const S
     a.sizes = d_sizes;
     a.err = (uint32_t *)wsb;
     SizeCtx *ctx = (SizeCtx *)(wsb + 8);
+    uint16_t *adv_tab = (uint16_t *)(wsb + 8 + 3 * kCtxBytes);
     const uint64_t nt = n_tiles ? n_tiles : 1;
-    a.tile_words = (uint32_t *)(wsb + 8 + 3 * kCtxBytes);
-    a.prefix = (uint64_t *)(wsb + 8 + 3 * kCtxBytes + 4 * ((nt + 1) & ~1ull));
+    a.tile_words = (uint32_t *)(wsb + 8 + 3 * kCtxBytes + kAdvTabBytes);
+    a.prefix = (uint64_t *)(wsb + 8 + 3 * kCtxBytes + kAdvTabBytes + 4 * ((nt + 1) & ~1ull));
     uint64_t *sums = a.prefix + nt;
     a.n_tiles = n_tiles;
     a.variant = variant;
     a.tile_lo = 0;
     a.tile_hi = 0;
     a.ctx = ctx;
-    prep_kernel<<<1, kThreads, 0, st>>>(a, ctx, L[0], L[1], L[2], n_segs);
+    // the advanced-count tables serve the advanced classes (8..15) and the two selectors
+    const bool adv_tables = variant >= 8;
+    for (int g = 0; g < 3; g++)
+        if (L[g] && adv_tables)
+            adv_table_kernel<<<(kAdvTab + kThreads - 1) / kThreads, kThreads, 0, st>>>(a.T, L[g],
+                                                                                      adv_tab + (size_t)g * kAdvTab);
+    prep_kernel<<<1, kThreads, 0, st>>>(a, ctx, L[0], L[1], L[2], n_segs, adv_tables ? adv_tab : nullptr);
     const size_t dyn = 0;
     for (int g = 0; g < 3; g++) {
         const uint64_t ntg = tile_hi[g] - tile_lo[g];

@@ -122,9 +122,21 @@ __device__ __forceinline__ void unpack_part(const DevTables &T, const SizeCtx &C
     auto put = [&](uint32_t j, uint32_t d) {
         if (j < n) dst[j] = (V)(d + add);
     };
+    auto put_all = [&](uint32_t j, uint32_t d) { dst[j] = (V)(d + add); };
     if (!fam) {
-        // inverse of Sec. 3.1 Eq. (2): the k digits of word i, peeled from the lowest power
-        for (uint32_t i = i0; i < nwords; i += G) peel_digits<Wide>(pb, src[i], i * pb.k, pb.k, put);
+        // inverse of Sec. 3.1 Eq. (2): the k digits of word i, peeled from the lowest power.
+        // Words before the last hold k values each; only the last can hold fewer (its low
+        // digits are then padding), so only it checks positions.
+        // The next word's load is in flight while a word is peeled.
+        const uint32_t k = pb.k;
+        uint32_t i = i0;
+        uint64_t w = src[i];
+        for (; i + 1 < nwords; i += G) {
+            const uint64_t wn = i + G < nwords ? src[i + G] : 0;
+            peel_digits<Wide>(pb, w, i * k, k, put_all);
+            w = wn;
+        }
+        if (i < nwords) peel_digits<Wide>(pb, w, i * k, k, put);
         return;
     }
     if (pb.D) {
@@ -136,7 +148,11 @@ __device__ __forceinline__ void unpack_part(const DevTables &T, const SizeCtx &C
             const uint64_t qR = div_magic(X, e->mR);
             const uint64_t r = X - qR * e->R;  // r_i, the low part of the split value
             const uint32_t p = e->p;
-            peel_digits<Wide>(pb, qR, q, p, put);  // what remains on top is r'_{i-1}
+            // what remains on top is r'_{i-1}; every word before the last holds only values
+            if (i + 1 < nwords)
+                peel_digits<Wide>(pb, qR, q, p, put_all);
+            else
+                peel_digits<Wide>(pb, qR, q, p, put);
             // the value split between this word (r_i at the bottom) and the next (r'_i on top)
             if (q + p < n && i + 1 < nwords) {
                 uint32_t q1;
@@ -254,7 +270,42 @@ __device__ __forceinline__ void decode_tile(const DevTables &T, const uint8_t *i
 
         // ---- 3. threshold blocks: a main digit equal to T marks the next excess value; add min.
         //         Blocks with B = 1 have no words: every value is the minimum.
-        {
+        if (G <= 64) {
+            // A block's group lies in one wavefront: round r takes values r G .. r G + G - 1,
+            // one per lane (consecutive LDS addresses), and a ballot ranks the marks of the
+            // round. The round count depends only on L, so every lane of the wavefront votes.
+            const int c = live ? S.cls[blk] : 0;
+            const int t = c & 7;
+            const uint32_t Lb = live ? (uint32_t)min((uint64_t)L, lo.n - (b0 + blk) * L) : 0;
+            V *vals = s_val + (size_t)blk * L;
+            if (live && !t && S.rng[blk] == 0) {
+                const V m = (V)S.min[blk];
+                for (uint32_t j = g; j < Lb; j += G) vals[j] = m;
+            }
+            if (__ballot(t != 0)) {
+                const uint32_t lane = tid & 63;
+                const uint64_t gmask = (G == 64 ? ~0ull : ((1ull << G) - 1)) << (lane - g);
+                const uint64_t below = (1ull << lane) - 1;
+                const uint32_t Tb = t ? 1u << (bitlen64((uint64_t)S.rng[blk]) - t) : 0;
+                const uint32_t ne = t ? S.ne[blk] : 0;
+                const uint32_t bmin = t ? S.min[blk] : 0;
+                const bool exc_words = t && (uint64_t)S.rng[blk] + 1 - Tb > 1;  // else every excess is 0
+                const V *ex = s_exc + (t ? S.exoff[blk] : 0);
+                uint32_t run = 0;  // marks of the block in earlier rounds
+                for (uint32_t j = g; j - g < L; j += G) {
+                    const bool in = t && j < Lb;
+                    uint32_t d = in ? (uint32_t)vals[j] : 0;
+                    const bool hit = in && d == Tb;
+                    const uint64_t m = __ballot(hit) & gmask;
+                    if (hit) {
+                        const uint32_t pos = run + (uint32_t)__popcll(m & below);
+                        d = Tb + ((exc_words && pos < ne) ? (uint32_t)ex[pos] : 0u);
+                    }
+                    if (in) vals[j] = (V)(d + bmin);
+                    run += (uint32_t)__popcll(m);
+                }
+            }
+        } else {
             const int c = live ? S.cls[blk] : 0;
             const int t = c & 7;
             const uint32_t Lb = live ? (uint32_t)min((uint64_t)L, lo.n - (b0 + blk) * L) : 0;

@@ -140,10 +140,12 @@ struct SizeCtx {
     uint64_t kmax[65];
     uint32_t p1_k[32];
     uint32_t p1_adv[32];
+    const uint16_t *advL;  // advanced words of a full block for every base <= 2^16 + 1, or nullptr
 };
 
-__device__ inline void fill_size_ctx(const DevTables &T, uint32_t L, SizeCtx &C) {
+__device__ inline void fill_size_ctx(const DevTables &T, uint32_t L, SizeCtx &C, const uint16_t *advL = nullptr) {
     const uint32_t t = threadIdx.x;
+    if (t == 200) C.advL = advL;
     if (t < 65) C.kmax[t] = T.kmax[t];
     if (t >= 96 && t < 128) {
         const uint32_t j = t - 96;
@@ -179,6 +181,7 @@ __device__ inline uint32_t fam_words(const DevTables &T, const SizeCtx &C, int f
     const uint32_t k = k_fast(C, base);
     if (!fam) return udiv_small(n + k - 1, k);
     if (n <= k) return 1;
+    if (n == full && C.advL && base <= kAtlasDirect) return C.advL[base];
     const uint64_t bm1 = base - 1;
     if ((bm1 & (bm1 - 1)) == 0 && n == full) return C.p1_adv[bitlen64(bm1) - 1];  // base 2^j + 1
     const int ai = atlas_index(base);
@@ -299,9 +302,28 @@ __device__ __forceinline__ uint32_t hist_bin(const Hist16 &h, int b) {
 // ---------------------------------------------------------------------------------------
 // Digit arithmetic in 32-bit chunks (see Chunk).
 // ---------------------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t div32_magic(uint32_t x, uint32_t m, uint32_t sh) {
-    const uint32_t t = __umulhi(m, x);
-    return (t + ((x - t) >> 1)) >> sh;
+// Peels cnt base-B digits off a chunk value xf < 2^32 (held exactly in binary64), lowest
+// first, to put(--j, digit); returns what remains. Each quotient is trunc(fma(x, rB, rB/2)),
+// rB = 1/B rounded to nearest: that is (x + 1/2) / B within a relative 2^-52, an error below
+// 2^-20 / B, while (x + 1/2) / B lies at least 1/(2B) from every integer; so the truncation
+// is floor(x / B) exactly, and fma(-q, B, x) is the exact remainder.
+template <typename Put>
+__device__ __forceinline__ double chunk_digits(double xf, double rB, double hB, double Bf, uint32_t &j, uint32_t cnt,
+                                               Put put) {
+    uint32_t m = cnt;
+    for (; m >= 2; m -= 2) {
+        const double q0 = __builtin_trunc(__builtin_fma(xf, rB, hB));
+        put(--j, (uint32_t)__builtin_fma(-q0, Bf, xf));
+        const double q1 = __builtin_trunc(__builtin_fma(q0, rB, hB));
+        put(--j, (uint32_t)__builtin_fma(-q1, Bf, q0));
+        xf = q1;
+    }
+    if (m) {
+        const double q0 = __builtin_trunc(__builtin_fma(xf, rB, hB));
+        put(--j, (uint32_t)__builtin_fma(-q0, Bf, xf));
+        xf = q0;
+    }
+    return xf;
 }
 
 // Resolved constants of one base for packing / unpacking a part of a block.
@@ -371,29 +393,18 @@ __device__ __forceinline__ uint64_t peel_digits(const PartBase &pb, uint64_t X, 
         }
         return X;
     }
-    const uint32_t B = (uint32_t)pb.base, h = pb.ch.h;
+    const uint32_t h = pb.ch.h;
+    const double rB = pb.ch.rB, hB = 0.5 * rB, Bf = (double)(uint32_t)pb.base;
     uint32_t j = j0 + cnt;
     uint32_t rem = cnt;
     while (rem >= h) {
         const uint64_t q = div_magic(X, pb.ch.mP);
-        uint32_t x = (uint32_t)(X - q * pb.ch.P);
+        chunk_digits((double)(uint32_t)(X - q * pb.ch.P), rB, hB, Bf, j, h, put);
         X = q;
-        for (uint32_t m = 0; m < h; m++) {
-            const uint32_t qq = div32_magic(x, pb.ch.m32, pb.ch.sh32);
-            put(--j, x - __umul24(qq, B));
-            x = qq;
-        }
         rem -= h;
     }
-    if (rem) {
-        uint32_t x = (uint32_t)X;  // fewer than h digits (plus a top digit) remain: X < B^h < 2^32
-        for (uint32_t m = 0; m < rem; m++) {
-            const uint32_t qq = div32_magic(x, pb.ch.m32, pb.ch.sh32);
-            put(--j, x - __umul24(qq, B));
-            x = qq;
-        }
-        X = x;
-    }
+    // fewer than h digits (plus a top digit) remain: X < B^h < 2^32
+    if (rem) X = (uint32_t)chunk_digits((double)(uint32_t)X, rB, hB, Bf, j, rem, put);
     return X;
 }
 

@@ -37,14 +37,13 @@ struct Magic {
 // s_{i + lam} = s_i for i >= mu, so entries 0 .. mu+lam-1 describe every word.
 // Digits handled in 32-bit chunks: h digits per chunk with P = B^h < 2^32 and B^(h-1) < 2^24,
 // so a chunk is built by 24-bit multiply-adds and split from a word by one 64-bit magic
-// division by P; inside a chunk the digits come out by 32-bit magic division by B.
+// division by P; inside a chunk the digits come out by binary64 division by B (rB).
 // h = 0 when B >= 2^24 (digits then go one by one through 64-bit arithmetic).
 struct Chunk {
     Magic mP;      // 64-bit division by P
     uint32_t h;    // digits per chunk
     uint32_t P;    // B^h
-    uint32_t m32;  // 32-bit magic for B: q = (t + ((x - t) >> 1)) >> sh32, t = mulhi32(m32, x)
-    uint32_t sh32;
+    double rB;     // 1 / B rounded to nearest binary64
 };
 
 struct BaseDesc {
