@@ -479,12 +479,12 @@ __global__ __launch_bounds__(kThreads) void pack_kernel(CompressArgs a) {
     __shared__ uint16_t s_cpre[kThreads];  // threshold blocks: excess values before each lane's chunk
     __shared__ uint4 s_exc[kExcBytes / 16];  // compacted excess lists of the tile, when they fit
     __shared__ uint16_t s_exoff[kMaxTileBlocks];
-    __shared__ uint32_t s_extot;
     __shared__ V s_min[kMaxTileBlocks], s_rng[kMaxTileBlocks];  // at the element width
-    __shared__ uint16_t s_ne[kMaxTileBlocks], s_off[kMaxTileBlocks];  // a tile holds at most 2304 words
+    __shared__ uint16_t s_ne[kMaxTileBlocks], s_off[kMaxTileBlocks + 1];  // a tile holds at most 2304 words
     __shared__ uint8_t s_cls[kMaxTileBlocks];
     __shared__ uint8_t s_perm[kMaxTileBlocks];  // block packed by lane group p
     __shared__ uint32_t s_red32[kThreads / 64];
+    __shared__ uint64_t s_red64[kThreads / 64];
     __shared__ SizeCtx s_C;
 
     const DevTables &T = a.T;
@@ -492,6 +492,7 @@ __global__ __launch_bounds__(kThreads) void pack_kernel(CompressArgs a) {
     const int variant = a.variant;
     const bool fixed0 = (variant == 0 || variant == 8);
     copy_size_ctx(a.ctx, s_C);
+    __syncthreads();  // the size tables are read before the first barrier of a tile
     for (uint64_t gt = a.tile_lo + blockIdx.x; gt < a.tile_hi; gt = kPersist ? gt + gridDim.x : a.tile_hi) {
         const SegDesc sd = seg_of(a, gt);
         const Layout &lo = sd.lo;
@@ -505,35 +506,46 @@ __global__ __launch_bounds__(kThreads) void pack_kernel(CompressArgs a) {
         // the tile's place in its stream's payload, fetched early
         const uint64_t base_off = a.prefix[gt] - a.prefix[sd.tile0];
         const V *s_val = stage_tile<W>(sd.data, v0, nvt, s_raw);
-        // the tile's block arrays, as the statistics launch wrote them
+        // the tile's block arrays, as the statistics launch wrote them, and each block's words.
+        // One scan of packed fields gives each block its word offset, its place among the
+        // tile's excess values and its lane group (basic blocks first, then advanced ones, so
+        // that wavefronts mostly run one family's code).
+        uint64_t key = 0;
         if (tid < nbt) {
             const uint64_t gb = b0 + tid;
-            s_min[tid] = (V)get_le(so + lo.off_min + gb * W, W);
-            s_rng[tid] = (V)get_le(so + lo.off_range + gb * W, W);
-            s_cls[tid] = (lo.flags & kFlagClass) ? so[lo.off_class + gb] : (uint8_t)variant;
-            s_ne[tid] = (lo.flags & kFlagNe)
-                            ? (uint16_t)get_le(so + lo.off_ne + gb * ((lo.flags & kFlagNe16) ? 2 : 1),
-                                               (lo.flags & kFlagNe16) ? 2 : 1)
-                            : (uint16_t)0;
+            const uint32_t mn = (uint32_t)get_le(so + lo.off_min + gb * W, W);
+            const uint32_t rg = (uint32_t)get_le(so + lo.off_range + gb * W, W);
+            const int c = (lo.flags & kFlagClass) ? so[lo.off_class + gb] : variant;
+            const uint32_t ne = (lo.flags & kFlagNe) ? (uint32_t)get_le(so + lo.off_ne + gb * ((lo.flags & kFlagNe16) ? 2 : 1),
+                                                                        (lo.flags & kFlagNe16) ? 2 : 1)
+                                                     : 0u;
+            s_min[tid] = (V)mn;
+            s_rng[tid] = (V)rg;
+            s_cls[tid] = (uint8_t)c;
+            s_ne[tid] = (uint16_t)ne;
+            const uint32_t Lb = (uint32_t)min((uint64_t)L, lo.n - gb * L);
+            const uint64_t B = (uint64_t)rg + 1;
+            uint32_t nwm;
+            uint32_t nw = class_words<(W == 4)>(T, s_C, L, c, Lb, B, bitlen64(B - 1), ne, nwm);
+            const uint32_t per = 8 / W, cap = (Lb + per - 1) / per;
+            nw = nw < cap ? nw : cap;
+            const bool adv = c >> 3;
+            // words (18 bits: a tile holds at most 2^14 values), excess values (18), basic
+            // blocks (9), advanced blocks (9)
+            key = (uint64_t)nw | ((uint64_t)(!fixed0 && (c & 7) ? ne : 0) << 18) | ((uint64_t)(adv ? 0 : 1) << 36) |
+                  ((uint64_t)(adv ? 1 : 0) << 45);
         }
-        // excess lists of the tile's threshold blocks: their places in the compaction buffer
-        if (!fixed0) {
-            const uint32_t mine = (tid < nbt && (s_cls[tid] & 7)) ? s_ne[tid] : 0;
-            uint32_t tot;
-            const uint32_t off = wg_excl_scan(mine, s_red32, &tot);
-            if (tid < nbt) s_exoff[tid] = (uint16_t)off;
-            if (tid == 0) s_extot = tot;
+        uint64_t tot;
+        const uint64_t exs = wg_excl_scan64(key, s_red64, &tot);
+        const uint32_t total = (uint32_t)(tot & 0x3FFFF), extot = (uint32_t)((tot >> 18) & 0x3FFFF);
+        if (tid < nbt) {
+            const uint32_t n_basic = (uint32_t)((tot >> 36) & 0x1FF);
+            s_off[tid] = (uint16_t)(exs & 0x3FFFF);
+            s_exoff[tid] = (uint16_t)((exs >> 18) & 0x3FFFF);
+            s_perm[(key >> 45) & 1 ? n_basic + (uint32_t)((exs >> 45) & 0x1FF) : (uint32_t)((exs >> 36) & 0x1FF)] =
+                (uint8_t)tid;
         }
-        // lane groups take the basic blocks first, then the advanced ones (stable), so that
-        // wavefronts mostly run one family's code
-        if (lo.flags & kFlagClass) {
-            const bool adv = tid < nbt && (s_cls[tid] >> 3);
-            uint32_t fam_tot;
-            const uint32_t fam_ex = wg_excl_scan(tid < nbt ? (adv ? 1u << 16 : 1u) : 0u, s_red32, &fam_tot);
-            if (tid < nbt) s_perm[adv ? (fam_tot & 0xFFFF) + (fam_ex >> 16) : (fam_ex & 0xFFFF)] = (uint8_t)tid;
-        } else if (tid < nbt) {
-            s_perm[tid] = (uint8_t)tid;
-        }
+        if (tid == 0) s_off[nbt] = (uint16_t)total;
         __syncthreads();
 
         const uint32_t G = kThreads / tb;
@@ -548,19 +560,14 @@ __global__ __launch_bounds__(kThreads) void pack_kernel(CompressArgs a) {
         const int cls = live ? s_cls[blk] : 0;
         const int tcls = cls & 7, fam = cls >> 3;
         const uint32_t ne = live ? s_ne[blk] : 0;
-        uint32_t nwm = 0, nw = 0;
-        if (live) {
-            nw = class_words<(W == 4)>(T, s_C, L, cls, Lb, B, beta, ne, nwm);
-            const uint32_t per = 8 / W, cap = (Lb + per - 1) / per;
-            nw = nw < cap ? nw : cap;
-            nwm = nwm < nw ? nwm : nw;
-        }
-        if (live && g == 0) s_off[blk] = (uint16_t)nw;
+        const uint32_t nw = live ? (uint32_t)s_off[blk + 1] - s_off[blk] : 0;
+        uint32_t nwm = tcls && live ? main_words<(W == 4)>(T, s_C, L, fam, tcls, Lb, beta) : 0;
+        nwm = nwm < nw ? nwm : nw;
         const uint64_t Th = tcls ? (1ull << (beta - tcls)) : 0;
         // threshold blocks: count the excess values (d >= T) of every lane's chunk and, when the
         // tile's lists fit the buffer, compact them there in data order
         const uint32_t ch = (Lb + G - 1) / G;
-        const bool compact = !fixed0 && s_extot * W <= kExcBytes;
+        const bool compact = !fixed0 && extot * W <= kExcBytes;
         V *s_ex = (V *)s_exc;
         if (!fixed0) {
             const uint32_t j0 = g * ch < Lb ? g * ch : Lb, j1 = (g + 1) * ch < Lb ? (g + 1) * ch : Lb;
@@ -576,13 +583,8 @@ __global__ __launch_bounds__(kThreads) void pack_kernel(CompressArgs a) {
                     if (d >= Th && pos < ne) ex[pos++] = (V)(d - Th);
                 }
             }
+            __syncthreads();
         }
-        __syncthreads();
-        uint32_t total;
-        const uint32_t my = tid < nbt ? s_off[tid] : 0;
-        const uint32_t ex_off = wg_excl_scan(my, s_red32, &total);
-        if (tid < nbt) s_off[tid] = (uint16_t)ex_off;
-        __syncthreads();
 
         // the offset is checked against the bound before anything is written at it
         const uint64_t max_off = b0 * ((L + (8 / W) - 1) / (8 / W));

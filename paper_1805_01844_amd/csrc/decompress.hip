@@ -63,13 +63,12 @@ struct DecShared {
     uint4 raw[kTileBytes / 16];  // decoded digits / values of the tile
     uint4 exc[kDecExcBytes / 16];  // decoded excess lists of the tile, when they fit
     uint16_t exoff[kMaxTileBlocks];  // each threshold block's place among the tile's excess values
-    uint32_t extot;
     uint32_t min[kMaxTileBlocks], rng[kMaxTileBlocks], ne[kMaxTileBlocks];
     uint32_t nwm[kMaxTileBlocks], off[kMaxTileBlocks + 1];
     uint8_t cls[kMaxTileBlocks];
     uint8_t perm[kMaxTileBlocks];  // block taken by lane group p: basic blocks first, then advanced
     uint32_t red32[kThreads / 64];
-    int bad;
+    uint64_t red64[kThreads / 64];
     SizeCtx C;
 };
 
@@ -114,11 +113,10 @@ __device__ __forceinline__ void unpack_adv_slow(const DevTables &T, uint64_t bas
 // Decodes words i0, i0+G, ... of one part (main digits or excess list) into dst[0 .. n);
 // `add` is added to every digit (the block minimum for plain blocks).
 template <typename V, bool Wide>
-__device__ __forceinline__ void unpack_part(const DevTables &T, const SizeCtx &C, uint64_t base, uint32_t n, int fam,
+__device__ __forceinline__ void unpack_part(const DevTables &T, const PartBase &pb, uint32_t n, int fam,
                                             uint32_t nwords, uint32_t i0, uint32_t G, const uint64_t *src, V *dst,
                                             uint32_t add) {
     if (nwords == 0 || i0 >= nwords) return;
-    const PartBase pb = resolve_base<Wide>(T, C, base);
     auto put = [&](uint32_t j, uint32_t d) {
         if (j < n) dst[j] = (V)(d + add);
     };
@@ -165,7 +163,7 @@ __device__ __forceinline__ void unpack_part(const DevTables &T, const SizeCtx &C
         return;
     }
     // base outside the tables (u32 data only)
-    if (Wide) unpack_adv_slow<V>(T, base, n, nwords, i0, G, src, dst, add);
+    if (Wide) unpack_adv_slow<V>(T, pb.base, n, nwords, i0, G, src, dst, add);
 }
 
 // Decodes tile `tile` of the stream at `in` (layout lo, pw payload words, fixed class of a
@@ -187,13 +185,15 @@ __device__ __forceinline__ void decode_tile(const DevTables &T, const uint8_t *i
         const uint32_t nbt = (uint32_t)min((uint64_t)tb, lo.n_blocks - b0);
         const uint64_t v0 = b0 * L;
         const uint32_t nvt = (uint32_t)min((uint64_t)nbt * L, lo.n - v0);
-        if (tid == 0) S.bad = 0;
-        __syncthreads();
         // ---- 1. block arrays of the tile and word counts (the tile's index entries are
-        //         fetched at once, alongside)
+        //         fetched at once, alongside). One scan of packed fields gives each block its
+        //         word offset, its place among the tile's excess values and its lane group
+        //         (basic blocks first, then advanced ones, so that wavefronts mostly run one
+        //         family's code), and counts blocks with invalid fields.
         const uint64_t base_off = idx[tile];
         const uint64_t next_off = (tile + 1 < lo.n_tiles) ? idx[tile + 1] : pw;
-        uint32_t nw = 0;
+        uint64_t key = 0;
+        bool adv = false;
         if (tid < nbt) {
             const uint64_t gb = b0 + tid;
             const uint32_t bmin = (uint32_t)get_le(in + lo.off_min + gb * W, W);
@@ -204,38 +204,34 @@ __device__ __forceinline__ void decode_tile(const DevTables &T, const uint8_t *i
             const uint64_t B = (uint64_t)rng + 1;
             const uint32_t beta = bitlen64(B - 1);
             const int t = c & 7;
-            const bool ok = c < 16 && t <= (int)beta && ne <= Lb && (t != 0 || ne == 0) && (uint64_t)bmin + rng <= vmaxw;
-            uint32_t nwm = 0;
+            bool ok = c < 16 && t <= (int)beta && ne <= Lb && (t != 0 || ne == 0) && (uint64_t)bmin + rng <= vmaxw;
+            uint32_t nwm = 0, nw = 0;
             if (ok) nw = class_words<(W == 4)>(T, S.C, L, c, Lb, B, beta, ne, nwm);
-            if (!ok) S.bad = 1;
+            ok = ok && nw <= 2 * Lb;  // each part takes at most one word per value
+            if (!ok) nw = nwm = 0;
             S.min[tid] = bmin;
             S.rng[tid] = rng;
             S.cls[tid] = (uint8_t)(ok ? c : 0);
             S.ne[tid] = ne;
             S.nwm[tid] = nwm;
+            adv = ok && (c >> 3);
+            // words (18 bits: a tile holds at most 2^14 values), excess values (18), basic
+            // blocks (9), advanced blocks (9), invalid blocks (9)
+            key = (uint64_t)nw | ((uint64_t)(ok && t ? ne : 0) << 18) | ((uint64_t)(adv ? 0 : 1) << 36) |
+                  ((uint64_t)(adv ? 1 : 0) << 45) | ((uint64_t)(ok ? 0 : 1) << 54);
         }
-        // excess lists of the tile's threshold blocks: their places in the decoded excess buffer
-        {
-            const uint32_t mine = (tid < nbt && (S.cls[tid] & 7)) ? S.ne[tid] : 0;
-            uint32_t tot;
-            const uint32_t off = wg_excl_scan(mine, S.red32, &tot);
-            if (tid < nbt) S.exoff[tid] = (uint16_t)off;
-            if (tid == 0) S.extot = tot;
+        uint64_t tot;
+        const uint64_t ex = wg_excl_scan64(key, S.red64, &tot);
+        const uint32_t tile_words = (uint32_t)(tot & 0x3FFFF), extot = (uint32_t)((tot >> 18) & 0x3FFFF);
+        const uint32_t n_basic = (uint32_t)((tot >> 36) & 0x1FF), n_bad = (uint32_t)(tot >> 54);
+        if (tid < nbt) {
+            S.off[tid] = (uint32_t)(ex & 0x3FFFF);
+            S.exoff[tid] = (uint16_t)((ex >> 18) & 0x3FFFF);
+            S.perm[adv ? n_basic + (uint32_t)((ex >> 45) & 0x1FF) : (uint32_t)((ex >> 36) & 0x1FF)] = (uint8_t)tid;
         }
-        uint32_t tile_words;
-        const uint32_t ex = wg_excl_scan(nw, S.red32, &tile_words);
-        if (tid < nbt) S.off[tid] = ex;
         if (tid == 0) S.off[nbt] = tile_words;
-        // lane groups take the basic blocks first, then the advanced ones (stable), so that
-        // wavefronts mostly run one family's code
-        {
-            const bool adv = tid < nbt && (S.cls[tid] >> 3);
-            uint32_t fam_tot;
-            const uint32_t fam_ex = wg_excl_scan(tid < nbt ? (adv ? 1u << 16 : 1u) : 0u, S.red32, &fam_tot);
-            if (tid < nbt) S.perm[adv ? (fam_tot & 0xFFFF) + (fam_ex >> 16) : (fam_ex & 0xFFFF)] = (uint8_t)tid;
-        }
         __syncthreads();
-        if (S.bad || base_off > pw || next_off > pw || next_off != base_off + tile_words) {
+        if (n_bad || base_off > pw || next_off > pw || next_off != base_off + tile_words) {
             if (tid == 0) set_status(status, PCOMP_ECORRUPT);
             __syncthreads();
             return;
@@ -243,7 +239,7 @@ __device__ __forceinline__ void decode_tile(const DevTables &T, const uint8_t *i
         const uint64_t *payload = payload_all + base_off;
         // decoded excess digits go to LDS when they fit, else to the tile's own output range,
         // which nothing reads or writes until the final store of the tile
-        V *s_exc = S.extot * W <= kDecExcBytes ? (V *)S.exc : (V *)(out + v0 * W);
+        V *s_exc = extot * W <= kDecExcBytes ? (V *)S.exc : (V *)(out + v0 * W);
 
         // ---- 2. decode: the lanes of a block's group take its words in turn
         const uint32_t grp = tid / G, g = tid % G;
@@ -258,18 +254,22 @@ __device__ __forceinline__ void decode_tile(const DevTables &T, const uint8_t *i
             const uint64_t *src = payload + S.off[blk];
             V *vals = s_val + (size_t)blk * L;
             if (t == 0) {
-                unpack_part<V, (W == 4)>(T, S.C, B, Lb, fam, nwb, g, G, src, vals, S.min[blk]);
+                unpack_part<V, (W == 4)>(T, resolve_base<(W == 4)>(T, S.C, B), Lb, fam, nwb, g, G, src, vals,
+                                         S.min[blk]);
             } else {
                 const uint64_t Th = 1ull << (bitlen64(B - 1) - t);
                 const uint32_t nwm = S.nwm[blk];
-                unpack_part<V, (W == 4)>(T, S.C, Th + 1, Lb, fam, nwm, g, G, src, vals, 0);
-                unpack_part<V, (W == 4)>(T, S.C, B - Th, S.ne[blk], fam, nwb - nwm, g, G, src + nwm, s_exc + S.exoff[blk], 0);
+                unpack_part<V, (W == 4)>(T, resolve_base<(W == 4)>(T, S.C, Th + 1), Lb, fam, nwm, g, G, src, vals,
+                                         S.min[blk]);
+                unpack_part<V, (W == 4)>(T, resolve_base<(W == 4)>(T, S.C, B - Th), S.ne[blk], fam, nwb - nwm, g, G,
+                                         src + nwm, s_exc + S.exoff[blk], 0);
             }
         }
         __syncthreads();
 
-        // ---- 3. threshold blocks: a main digit equal to T marks the next excess value; add min.
-        //         Blocks with B = 1 have no words: every value is the minimum.
+        // ---- 3. threshold blocks: a main value equal to min + T (digit T) marks the next excess
+        //         value, which is added to it. Blocks with B = 1 have no words: every value is
+        //         the minimum.
         if (G <= 64) {
             // A block's group lies in one wavefront: round r takes values r G .. r G + G - 1,
             // one per lane (consecutive LDS addresses), and a ballot ranks the marks of the
@@ -288,20 +288,17 @@ __device__ __forceinline__ void decode_tile(const DevTables &T, const uint8_t *i
                 const uint64_t below = (1ull << lane) - 1;
                 const uint32_t Tb = t ? 1u << (bitlen64((uint64_t)S.rng[blk]) - t) : 0;
                 const uint32_t ne = t ? S.ne[blk] : 0;
-                const uint32_t bmin = t ? S.min[blk] : 0;
+                const uint32_t mark = t ? S.min[blk] + Tb : 0;
                 const bool exc_words = t && (uint64_t)S.rng[blk] + 1 - Tb > 1;  // else every excess is 0
                 const V *ex = s_exc + (t ? S.exoff[blk] : 0);
                 uint32_t run = 0;  // marks of the block in earlier rounds
                 for (uint32_t j = g; j - g < L; j += G) {
-                    const bool in = t && j < Lb;
-                    uint32_t d = in ? (uint32_t)vals[j] : 0;
-                    const bool hit = in && d == Tb;
+                    const bool hit = t && j < Lb && (uint32_t)vals[j] == mark;
                     const uint64_t m = __ballot(hit) & gmask;
                     if (hit) {
                         const uint32_t pos = run + (uint32_t)__popcll(m & below);
-                        d = Tb + ((exc_words && pos < ne) ? (uint32_t)ex[pos] : 0u);
+                        vals[j] = (V)(mark + ((exc_words && pos < ne) ? (uint32_t)ex[pos] : 0u));
                     }
-                    if (in) vals[j] = (V)(d + bmin);
                     run += (uint32_t)__popcll(m);
                 }
             }
@@ -312,11 +309,12 @@ __device__ __forceinline__ void decode_tile(const DevTables &T, const uint8_t *i
             const uint32_t ch = (Lb + G - 1) / G;
             const uint32_t j0 = g * ch < Lb ? g * ch : Lb, j1 = (g + 1) * ch < Lb ? (g + 1) * ch : Lb;
             V *vals = s_val + (size_t)blk * L;
-            uint32_t Tb = 0;
+            uint32_t Tb = 0, mark = 0;
             uint32_t cnt = 0;
             if (t) {
                 Tb = 1u << (bitlen64((uint64_t)S.rng[blk]) - t);
-                for (uint32_t j = j0; j < j1; j++) cnt += (uint32_t)vals[j] == Tb;
+                mark = S.min[blk] + Tb;
+                for (uint32_t j = j0; j < j1; j++) cnt += (uint32_t)vals[j] == mark;
             }
             uint32_t pos = group_excl_scan(cnt, G, S.red32);
             if (live && !t && S.rng[blk] == 0) {
@@ -325,16 +323,13 @@ __device__ __forceinline__ void decode_tile(const DevTables &T, const uint8_t *i
             }
             if (t) {
                 const uint32_t ne = S.ne[blk];
-                const uint32_t bmin = S.min[blk];
                 const bool exc_words = (uint64_t)S.rng[blk] + 1 - Tb > 1;  // else every excess is 0
                 const V *ex = s_exc + S.exoff[blk];
                 for (uint32_t j = j0; j < j1; j++) {
-                    uint32_t d = vals[j];
-                    if (d == Tb) {
-                        d = Tb + ((exc_words && pos < ne) ? (uint32_t)ex[pos] : 0u);
+                    if ((uint32_t)vals[j] == mark) {
+                        vals[j] = (V)(mark + ((exc_words && pos < ne) ? (uint32_t)ex[pos] : 0u));
                         pos++;
                     }
-                    vals[j] = (V)(d + bmin);
                 }
             }
         }

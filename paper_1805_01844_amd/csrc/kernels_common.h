@@ -90,6 +90,27 @@ __device__ __forceinline__ uint32_t wg_excl_scan(uint32_t x, uint32_t *scratch, 
     return inc - x + add;
 }
 
+// Exclusive prefix sum of 64-bit x over the workgroup; *total gets the sum. It ends without
+// a barrier after reading scratch: the caller writes scratch again only after a later one.
+__device__ __forceinline__ uint64_t wg_excl_scan64(uint64_t x, uint64_t *scratch, uint64_t *total) {
+    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint64_t inc = x;
+    for (uint32_t o = 1; o < 64; o <<= 1) {
+        const uint64_t y = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += y;
+    }
+    if (lane == 63) scratch[wave] = inc;
+    __syncthreads();
+    uint64_t add = 0, tot = 0;
+    for (uint32_t w = 0; w < kThreads / 64; w++) {
+        const uint64_t v = scratch[w];
+        add += w < wave ? v : 0;
+        tot += v;
+    }
+    *total = tot;
+    return inc - x + add;
+}
+
 // Scalar-register copies of values that every lane of the wavefront holds equally (segment
 // descriptors read from memory): keeps them out of vector registers.
 __device__ __forceinline__ uint32_t uni32(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
