@@ -367,17 +367,30 @@ __global__ __launch_bounds__(kThreads) void stats_kernel(CompressArgs a) {
                 const uint64_t k8 = ((uint64_t)class_words<(W == 4)>(T, s_C, L, 8, Lb, B, beta, 0, nwm) << 8) | 8;
                 key = k8 < key ? k8 : key;
             }
-            for (int c = (int)g; c < 16; c += (int)G) {
-                const int t = c & 7;
-                if (t == 0 || t > (int)beta) continue;
+            // lanes split the thresholds t; each sizes both families of its t, which share the
+            // excess base B - T and its digits per word
+            for (int t = 1 + (int)g; t < 8; t += (int)G) {
+                if (t > (int)beta) break;
                 uint32_t net = 0;
 #pragma unroll
                 for (int tt = 1; tt < 8; tt++) net = (t == tt) ? ne_t[tt] : net;  // no dynamic register index
-                const uint32_t lb = main_words<(W == 4)>(T, s_C, L, c >> 3, t, Lb, beta) + (net ? 1 : 0);
-                if ((((uint64_t)lb << 8) | (uint64_t)c) >= key) continue;
-                const uint32_t nw = class_words<(W == 4)>(T, s_C, L, c, Lb, B, beta, net, nwm);
-                const uint64_t k2 = ((uint64_t)nw << 8) | (uint64_t)c;
-                key = k2 < key ? k2 : key;
+                const uint32_t m0 = main_words<(W == 4)>(T, s_C, L, 0, t, Lb, beta);
+                const uint32_t m1 = main_words<(W == 4)>(T, s_C, L, 1, t, Lb, beta);
+                const uint32_t one = net ? 1 : 0;
+                const bool try0 = ((((uint64_t)(m0 + one)) << 8) | (uint64_t)t) < key;
+                const bool try1 = ((((uint64_t)(m1 + one)) << 8) | (uint64_t)(8 + t)) < key;
+                if (!try0 && !try1) continue;
+                const uint64_t Be = B - (1ull << (beta - t));
+                uint32_t e0 = 0, e1 = 0;
+                if (net && Be > 1) {
+                    const uint32_t ke = k_fast(s_C, Be);
+                    e0 = udiv_small(net + ke - 1, ke);
+                    e1 = net <= ke ? 1 : fam_words<(W == 4)>(T, s_C, 1, net, Be, L);
+                }
+                const uint64_t k0 = ((uint64_t)(m0 + e0) << 8) | (uint64_t)t;
+                const uint64_t k1 = ((uint64_t)(m1 + e1) << 8) | (uint64_t)(8 + t);
+                key = (try0 && k0 < key) ? k0 : key;
+                key = (try1 && k1 < key) ? k1 : key;
             }
         } else if (live) {
             for (int c = (int)g; c < 16; c += (int)G) {
