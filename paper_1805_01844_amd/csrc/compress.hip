@@ -230,6 +230,7 @@ __global__ __launch_bounds__(kThreads) void stats_kernel(CompressArgs a) {
     __shared__ uint64_t s_red64[kThreads / 64];
     __shared__ uint32_t s_red32[kThreads / 64];
     __shared__ SizeCtx s_C;
+    __shared__ float s_model[kLearned ? kMlpParams : 1];  // the selector's parameters, per workgroup
 
     const DevTables &T = a.T;
     const uint32_t tid = threadIdx.x;
@@ -237,6 +238,10 @@ __global__ __launch_bounds__(kThreads) void stats_kernel(CompressArgs a) {
     const bool fixed0 = (variant == 0 || variant == 8);
     const bool learned = kLearned;  // the variant is PCOMP_SELECT_LEARNED
     copy_size_ctx(a.ctx, s_C);
+    // lanes read different weights at once: LDS serves those reads without the constant cache's
+    // serialisation (read before the first tile's barrier)
+    if (kLearned)
+        for (uint32_t i = tid; i < (uint32_t)kMlpParams; i += kThreads) s_model[i] = c_model[i];
     for (uint64_t gt = a.tile_lo + blockIdx.x; gt < a.tile_hi; gt = kPersist ? gt + gridDim.x : a.tile_hi) {
         const SegDesc sd = seg_of(a, gt);
         const Layout &lo = sd.lo;
@@ -305,9 +310,9 @@ __global__ __launch_bounds__(kThreads) void stats_kernel(CompressArgs a) {
                 float x[kMlpIn];
                 block_features(H, Lb, vmin, vmax, x);
                 for (uint32_t j = g; j < (uint32_t)kMlpHid; j += G) {
-                    float acc = c_model[kMlpB1 + j];
+                    float acc = s_model[kMlpB1 + j];
 #pragma unroll
-                    for (int i = 0; i < kMlpIn; i++) acc = __builtin_fmaf(c_model[kMlpW1 + j * kMlpIn + i], x[i], acc);
+                    for (int i = 0; i < kMlpIn; i++) acc = __builtin_fmaf(s_model[kMlpW1 + j * kMlpIn + i], x[i], acc);
                     s_h[blk * kMlpHid + j] = acc > 0.0f ? acc : 0.0f;
                 }
             }
@@ -315,9 +320,9 @@ __global__ __launch_bounds__(kThreads) void stats_kernel(CompressArgs a) {
             uint64_t best = 0;  // (order-preserving score bits, 15 - class): the first top score
             if (live) {
                 for (uint32_t k = g; k < (uint32_t)kMlpOut; k += G) {
-                    float acc = c_model[kMlpB2 + k];
+                    float acc = s_model[kMlpB2 + k];
                     for (int j = 0; j < kMlpHid; j++)
-                        acc = __builtin_fmaf(c_model[kMlpW2 + k * kMlpHid + j], s_h[blk * kMlpHid + j], acc);
+                        acc = __builtin_fmaf(s_model[kMlpW2 + k * kMlpHid + j], s_h[blk * kMlpHid + j], acc);
                     uint32_t u = __float_as_uint(acc == 0.0f ? 0.0f : acc);
                     u = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
                     const uint64_t key = ((uint64_t)u << 32) | (uint64_t)(15 - k);
@@ -348,7 +353,7 @@ __global__ __launch_bounds__(kThreads) void stats_kernel(CompressArgs a) {
                 for (int b = 0; b < 16; b++) H[b] = (f[b >> 1] >> (16 * (b & 1))) & 0xFFFF;
                 float x[kMlpIn], sc[kMlpOut];
                 block_features(H, f[10], f[8], f[9], x);
-                mlp_scores([](int i) { return c_model[i]; }, x, sc);
+                mlp_scores([&](int i) { return s_model[i]; }, x, sc);
                 s_pred[tid] = (uint8_t)argmax16(sc);
             }
             __syncthreads();
