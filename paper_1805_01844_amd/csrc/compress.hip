@@ -215,6 +215,82 @@ __device__ __forceinline__ const typename Elem<W>::T *stage_tile(const uint8_t *
     return (const V *)(s_bytes + head);
 }
 
+// Staging of a tile's input with every load in flight at once: the 16-byte chunks that lie
+// inside the segment go through buffer loads into registers (a chunk that is not loaded gets an
+// offset past the buffer's range, which reads zeros without touching memory, so the loads are
+// unconditional; buffer loads are counted apart from LDS operations), and are then stored to
+// LDS; chunks at the segment's edges (and a 1025th chunk of an unaligned full tile) are copied
+// element by element.
+constexpr uint32_t kStageChunks = kTileBytes / 16 / kThreads;
+static_assert(kStageChunks == 4, "four chunks per thread");
+struct Staged {
+    uint4 c0, c1, c2, c3;  // separate members, not an array: they stay in registers
+};
+struct TileRef {
+    const uint8_t *gbase;  // 16-byte aligned address at or below the tile's first value
+    uint32_t head, span;   // the tile's bytes are [head, span) from gbase
+    const uint8_t *lo, *hi;  // the segment's bytes
+};
+
+template <int W>
+__device__ __forceinline__ TileRef tile_ref(const SegDesc &sd, uint64_t v0, uint32_t nvt) {
+    TileRef t;
+    const uintptr_t addr = (uintptr_t)(sd.data + v0 * W);
+    t.head = (uint32_t)(addr & 15);
+    t.gbase = (const uint8_t *)(addr - t.head);
+    t.span = t.head + nvt * W;
+    t.lo = sd.data;
+    t.hi = sd.data + sd.lo.n * W;
+    return t;
+}
+
+__device__ __forceinline__ bool chunk_inside(const TileRef &t, uint32_t c) {
+    const uint8_t *p = t.gbase + (c << 4);
+    return p >= t.lo && p + 16 <= t.hi;
+}
+
+__device__ __forceinline__ void tile_fetch(const TileRef &t, Staged &r) {
+    const uint32_t nchunks = (t.span + 15) >> 4;
+    const auto rsrc = __builtin_amdgcn_make_buffer_rsrc((void *)t.gbase, (short)0, (int)(nchunks << 4), 0x00020000);
+    auto get = [&](uint32_t k) -> uint4 {
+        const uint32_t c = threadIdx.x + k * kThreads;
+        const bool ok = c < nchunks && chunk_inside(t, c);
+        const auto v = __builtin_amdgcn_raw_buffer_load_b128(rsrc, ok ? (int)(c << 4) : (int)0x40000000, 0, 0);
+        return make_uint4(v[0], v[1], v[2], v[3]);
+    };
+    r.c0 = get(0);
+    r.c1 = get(1);
+    r.c2 = get(2);
+    r.c3 = get(3);
+}
+
+template <int W>
+__device__ __forceinline__ const typename Elem<W>::T *tile_commit(const TileRef &t, const Staged &r, uint4 *s_raw) {
+    typedef typename Elem<W>::T V;
+    uint8_t *s_bytes = (uint8_t *)s_raw;
+    const uint32_t nchunks = (t.span + 15) >> 4;
+    auto copy_elems = [&](uint32_t c) {
+        const uint32_t cb = c << 4;
+        const uint32_t e0 = cb > t.head ? cb : t.head, e1 = cb + 16 < t.span ? cb + 16 : t.span;
+        for (uint32_t b = e0; b < e1; b += W) *(V *)(s_bytes + b) = *(const V *)(t.gbase + b);
+    };
+    auto put = [&](uint32_t k, const uint4 &v) {
+        const uint32_t c = threadIdx.x + k * kThreads;
+        if (c < nchunks) {
+            if (chunk_inside(t, c))
+                s_raw[c] = v;
+            else
+                copy_elems(c);
+        }
+    };
+    put(0, r.c0);
+    put(1, r.c1);
+    put(2, r.c2);
+    put(3, r.c3);
+    if (threadIdx.x + kStageChunks * kThreads < nchunks) copy_elems(threadIdx.x + kStageChunks * kThreads);
+    return (const V *)(s_bytes + t.head);
+}
+
 __device__ __forceinline__ void copy_size_ctx(const SizeCtx *g, SizeCtx &s) {
     static_assert(sizeof(SizeCtx) / 4 <= kThreads, "one word per thread");
     if (threadIdx.x < sizeof(SizeCtx) / 4) ((uint32_t *)&s)[threadIdx.x] = ((const uint32_t *)g)[threadIdx.x];
@@ -251,7 +327,16 @@ __global__ __launch_bounds__(kThreads) void stats_kernel(CompressArgs a) {
         const uint32_t nbt = (uint32_t)min((uint64_t)tb, lo.n_blocks - b0);
         const uint64_t v0 = b0 * L;
         const uint32_t nvt = (uint32_t)min((uint64_t)nbt * L, lo.n - v0);
-        const V *s_val = stage_tile<W>(sd.data, v0, nvt, s_raw);
+        // one workgroup per tile: all of its loads at once (persistent grids keep fewer registers)
+        const V *s_val;
+        if (kPersist) {
+            s_val = stage_tile<W>(sd.data, v0, nvt, s_raw);
+        } else {
+            const TileRef tr = tile_ref<W>(sd, v0, nvt);
+            Staged stg;
+            tile_fetch(tr, stg);
+            s_val = tile_commit<W>(tr, stg, s_raw);
+        }
         __syncthreads();
 
         // per block: min / max (B = v_max - v_min + 1) and excess counts
@@ -523,7 +608,15 @@ __global__ __launch_bounds__(kThreads) void pack_kernel(CompressArgs a) {
         const uint32_t nvt = (uint32_t)min((uint64_t)nbt * L, lo.n - v0);
         // the tile's place in its stream's payload, fetched early
         const uint64_t base_off = a.prefix[gt] - a.prefix[sd.tile0];
-        const V *s_val = stage_tile<W>(sd.data, v0, nvt, s_raw);
+        // one workgroup per tile: the tile's input is in flight while the block arrays are read
+        // (persistent grids stage it first and keep fewer registers)
+        const TileRef tr = tile_ref<W>(sd, v0, nvt);
+        Staged stg;
+        const V *s_val = nullptr;
+        if (kPersist)
+            s_val = stage_tile<W>(sd.data, v0, nvt, s_raw);
+        else
+            tile_fetch(tr, stg);
         // the tile's block arrays, as the statistics launch wrote them, and each block's words.
         // One scan of packed fields gives each block its word offset, its place among the
         // tile's excess values and its lane group (basic blocks first, then advanced ones, so
@@ -553,6 +646,7 @@ __global__ __launch_bounds__(kThreads) void pack_kernel(CompressArgs a) {
             key = (uint64_t)nw | ((uint64_t)(!fixed0 && (c & 7) ? ne : 0) << 18) | ((uint64_t)(adv ? 0 : 1) << 36) |
                   ((uint64_t)(adv ? 1 : 0) << 45);
         }
+        if (!kPersist) s_val = tile_commit<W>(tr, stg, s_raw);
         uint64_t tot;
         const uint64_t exs = wg_excl_scan64(key, s_red64, &tot);
         const uint32_t total = (uint32_t)(tot & 0x3FFFF), extot = (uint32_t)((tot >> 18) & 0x3FFFF);
