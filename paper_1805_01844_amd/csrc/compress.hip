@@ -272,7 +272,8 @@ __device__ __forceinline__ const typename Elem<W>::T *tile_commit(const TileRef 
     auto copy_elems = [&](uint32_t c) {
         const uint32_t cb = c << 4;
         const uint32_t e0 = cb > t.head ? cb : t.head, e1 = cb + 16 < t.span ? cb + 16 : t.span;
-        for (uint32_t b = e0; b < e1; b += W) *(V *)(s_bytes + b) = *(const V *)(t.gbase + b);
+        for (uint32_t b = e0; b < e1; b += W)
+            *(V *)(s_bytes + b) = *(const __attribute__((address_space(1))) V *)(t.gbase + b);
     };
     auto put = [&](uint32_t k, const uint4 &v) {
         const uint32_t c = threadIdx.x + k * kThreads;

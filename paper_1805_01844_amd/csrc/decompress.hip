@@ -75,9 +75,9 @@ struct DecShared {
 // Advanced part whose base is outside the tables: each lane of the group walks the series
 // itself (the state of word i depends on every word before it) and decodes its own words
 // i0, i0 + G, ... (G a power of two), including the value split at the end of each.
-template <typename V>
+template <typename V, typename Dst>
 __device__ __forceinline__ void unpack_adv_slow(const DevTables &T, uint64_t base, uint32_t n, uint32_t nwords,
-                                                uint32_t i0, uint32_t G, const uint64_t *src, V *dst, uint32_t add) {
+                                                uint32_t i0, uint32_t G, const uint64_t *src, Dst dst, uint32_t add) {
     const SlowBase sb = slow_base(T, base);
     const Magic mB = magic_dev(base);
     uint32_t q = 0, p;
@@ -112,9 +112,9 @@ __device__ __forceinline__ void unpack_adv_slow(const DevTables &T, uint64_t bas
 
 // Decodes words i0, i0+G, ... of one part (main digits or excess list) into dst[0 .. n);
 // `add` is added to every digit (the block minimum for plain blocks).
-template <typename V, bool Wide>
+template <typename V, bool Wide, typename Dst>
 __device__ __forceinline__ void unpack_part(const DevTables &T, const PartBase &pb, uint32_t n, int fam,
-                                            uint32_t nwords, uint32_t i0, uint32_t G, const uint64_t *src, V *dst,
+                                            uint32_t nwords, uint32_t i0, uint32_t G, const uint64_t *src, Dst dst,
                                             uint32_t add) {
     if (nwords == 0 || i0 >= nwords) return;
     auto put = [&](uint32_t j, uint32_t d) {
@@ -239,7 +239,10 @@ __device__ __forceinline__ void decode_tile(const DevTables &T, const uint8_t *i
         const uint64_t *payload = payload_all + base_off;
         // decoded excess digits go to LDS when they fit, else to the tile's own output range,
         // which nothing reads or writes until the final store of the tile
-        V *s_exc = extot * W <= kDecExcBytes ? (V *)S.exc : (V *)(out + v0 * W);
+        // (the two places are kept apart in the code, so that each access uses its own address space)
+        const bool exc_lds = extot * W <= kDecExcBytes;
+        V *const l_exc = (V *)S.exc;
+        __attribute__((address_space(1))) V *const g_exc = (__attribute__((address_space(1))) V *)(out + v0 * W);
 
         // ---- 2. decode: the lanes of a block's group take its words in turn
         const uint32_t grp = tid / G, g = tid % G;
@@ -261,8 +264,11 @@ __device__ __forceinline__ void decode_tile(const DevTables &T, const uint8_t *i
                 const uint32_t nwm = S.nwm[blk];
                 unpack_part<V, (W == 4)>(T, resolve_base<(W == 4)>(T, S.C, Th + 1), Lb, fam, nwm, g, G, src, vals,
                                          S.min[blk]);
-                unpack_part<V, (W == 4)>(T, resolve_base<(W == 4)>(T, S.C, B - Th), S.ne[blk], fam, nwb - nwm, g, G,
-                                         src + nwm, s_exc + S.exoff[blk], 0);
+                const PartBase pe = resolve_base<(W == 4)>(T, S.C, B - Th);
+                if (exc_lds)
+                    unpack_part<V, (W == 4)>(T, pe, S.ne[blk], fam, nwb - nwm, g, G, src + nwm, l_exc + S.exoff[blk], 0);
+                else
+                    unpack_part<V, (W == 4)>(T, pe, S.ne[blk], fam, nwb - nwm, g, G, src + nwm, g_exc + S.exoff[blk], 0);
             }
         }
         __syncthreads();
@@ -290,14 +296,16 @@ __device__ __forceinline__ void decode_tile(const DevTables &T, const uint8_t *i
                 const uint32_t ne = t ? S.ne[blk] : 0;
                 const uint32_t mark = t ? S.min[blk] + Tb : 0;
                 const bool exc_words = t && (uint64_t)S.rng[blk] + 1 - Tb > 1;  // else every excess is 0
-                const V *ex = s_exc + (t ? S.exoff[blk] : 0);
+                const uint32_t eo = t ? S.exoff[blk] : 0;
                 uint32_t run = 0;  // marks of the block in earlier rounds
                 for (uint32_t j = g; j - g < L; j += G) {
                     const bool hit = t && j < Lb && (uint32_t)vals[j] == mark;
                     const uint64_t m = __ballot(hit) & gmask;
                     if (hit) {
                         const uint32_t pos = run + (uint32_t)__popcll(m & below);
-                        vals[j] = (V)(mark + ((exc_words && pos < ne) ? (uint32_t)ex[pos] : 0u));
+                        uint32_t e = 0;
+                        if (exc_words && pos < ne) e = exc_lds ? (uint32_t)l_exc[eo + pos] : (uint32_t)g_exc[eo + pos];
+                        vals[j] = (V)(mark + e);
                     }
                     run += (uint32_t)__popcll(m);
                 }
@@ -324,10 +332,12 @@ __device__ __forceinline__ void decode_tile(const DevTables &T, const uint8_t *i
             if (t) {
                 const uint32_t ne = S.ne[blk];
                 const bool exc_words = (uint64_t)S.rng[blk] + 1 - Tb > 1;  // else every excess is 0
-                const V *ex = s_exc + S.exoff[blk];
+                const uint32_t eo = S.exoff[blk];
                 for (uint32_t j = j0; j < j1; j++) {
                     if ((uint32_t)vals[j] == mark) {
-                        vals[j] = (V)(mark + ((exc_words && pos < ne) ? (uint32_t)ex[pos] : 0u));
+                        uint32_t e = 0;
+                        if (exc_words && pos < ne) e = exc_lds ? (uint32_t)l_exc[eo + pos] : (uint32_t)g_exc[eo + pos];
+                        vals[j] = (V)(mark + e);
                         pos++;
                     }
                 }
@@ -338,23 +348,23 @@ __device__ __forceinline__ void decode_tile(const DevTables &T, const uint8_t *i
         // ---- 4. coalesced store of the tile (16-byte stores where the output is aligned)
         {
             const uint8_t *sb = (const uint8_t *)S.raw;
-            uint8_t *gdst = out + v0 * W;
+            __attribute__((address_space(1))) uint8_t *gdst = (__attribute__((address_space(1))) uint8_t *)(out + v0 * W);
             const uint32_t head = (uint32_t)((16 - ((uintptr_t)gdst & 15)) & 15);
             const uint32_t nbytes = nvt * W;
             const uint32_t hb = head < nbytes ? head : nbytes;
-            for (uint32_t b = tid * W; b < hb; b += kThreads * W) *(V *)(gdst + b) = *(const V *)(sb + b);
+            for (uint32_t b = tid * W; b < hb; b += kThreads * W) *(__attribute__((address_space(1))) V *)(gdst + b) = *(const V *)(sb + b);
             const uint32_t body = (nbytes - hb) >> 4;
             if ((hb & 3) == 0) {
                 for (uint32_t c = tid; c < body; c += kThreads) {
                     const uint32_t *s32 = (const uint32_t *)(sb + hb + (c << 4));
-                    *(uint4 *)(gdst + hb + (c << 4)) = make_uint4(s32[0], s32[1], s32[2], s32[3]);
+                    *(__attribute__((address_space(1))) uint4 *)(gdst + hb + (c << 4)) = make_uint4(s32[0], s32[1], s32[2], s32[3]);
                 }
             } else {
                 for (uint32_t b = hb + tid * W; b < hb + (body << 4); b += kThreads * W)
-                    *(V *)(gdst + b) = *(const V *)(sb + b);
+                    *(__attribute__((address_space(1))) V *)(gdst + b) = *(const V *)(sb + b);
             }
             for (uint32_t b = hb + (body << 4) + tid * W; b < nbytes; b += kThreads * W)
-                *(V *)(gdst + b) = *(const V *)(sb + b);
+                *(__attribute__((address_space(1))) V *)(gdst + b) = *(const V *)(sb + b);
         }
         __syncthreads();
     }

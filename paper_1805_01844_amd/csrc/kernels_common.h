@@ -202,7 +202,8 @@ __device__ inline uint32_t fam_words(const DevTables &T, const SizeCtx &C, int f
     const uint32_t k = k_fast(C, base);
     if (!fam) return udiv_small(n + k - 1, k);
     if (n <= k) return 1;
-    if (n == full && C.advL && base <= kAtlasDirect) return C.advL[base];
+    if (n == full && C.advL && base <= kAtlasDirect)
+        return ((const __attribute__((address_space(1))) uint16_t *)C.advL)[base];  // global, not flat
     const uint64_t bm1 = base - 1;
     if ((bm1 & (bm1 - 1)) == 0 && n == full) return C.p1_adv[bitlen64(bm1) - 1];  // base 2^j + 1
     const int ai = atlas_index(base);
