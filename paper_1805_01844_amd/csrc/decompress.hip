@@ -357,7 +357,8 @@ __device__ __forceinline__ void decode_tile(const DevTables &T, const uint8_t *i
             if ((hb & 3) == 0) {
                 for (uint32_t c = tid; c < body; c += kThreads) {
                     const uint32_t *s32 = (const uint32_t *)(sb + hb + (c << 4));
-                    *(__attribute__((address_space(1))) uint4 *)(gdst + hb + (c << 4)) = make_uint4(s32[0], s32[1], s32[2], s32[3]);
+                    typedef uint32_t U32x4 __attribute__((ext_vector_type(4)));
+                    *(__attribute__((address_space(1))) U32x4 *)(gdst + hb + (c << 4)) = U32x4{s32[0], s32[1], s32[2], s32[3]};
                 }
             } else {
                 for (uint32_t b = hb + tid * W; b < hb + (body << 4); b += kThreads * W)
