@@ -277,9 +277,9 @@ __device__ __forceinline__ void decode_tile(const DevTables &T, const uint8_t *i
         //         value, which is added to it. Blocks with B = 1 have no words: every value is
         //         the minimum.
         if (G <= 64) {
-            // A block's group lies in one wavefront: round r takes values r G .. r G + G - 1,
-            // one per lane (consecutive LDS addresses), and a ballot ranks the marks of the
-            // round. The round count depends only on L, so every lane of the wavefront votes.
+            // A block's group lies in one wavefront and takes its values in rounds; ballots rank
+            // the marks of a round. The round count depends only on L, so every lane of the
+            // wavefront votes.
             const int c = live ? S.cls[blk] : 0;
             const int t = c & 7;
             const uint32_t Lb = live ? (uint32_t)min((uint64_t)L, lo.n - (b0 + blk) * L) : 0;
@@ -297,17 +297,50 @@ __device__ __forceinline__ void decode_tile(const DevTables &T, const uint8_t *i
                 const uint32_t mark = t ? S.min[blk] + Tb : 0;
                 const bool exc_words = t && (uint64_t)S.rng[blk] + 1 - Tb > 1;  // else every excess is 0
                 const uint32_t eo = t ? S.exoff[blk] : 0;
+                auto excess = [&](uint32_t pos) -> uint32_t {
+                    if (!exc_words || pos >= ne) return 0;
+                    return exc_lds ? (uint32_t)l_exc[eo + pos] : (uint32_t)g_exc[eo + pos];
+                };
                 uint32_t run = 0;  // marks of the block in earlier rounds
-                for (uint32_t j = g; j - g < L; j += G) {
-                    const bool hit = t && j < Lb && (uint32_t)vals[j] == mark;
-                    const uint64_t m = __ballot(hit) & gmask;
-                    if (hit) {
-                        const uint32_t pos = run + (uint32_t)__popcll(m & below);
-                        uint32_t e = 0;
-                        if (exc_words && pos < ne) e = exc_lds ? (uint32_t)l_exc[eo + pos] : (uint32_t)g_exc[eo + pos];
-                        vals[j] = (V)(mark + e);
+                if (((L * W) & 15) == 0) {
+                    // blocks start on 16-byte boundaries: a lane takes 16 bytes per round and
+                    // counts the marks among them; bit-sliced ballots of the counts give it the
+                    // marks of the group's lanes before it
+                    constexpr uint32_t per = 16 / W;
+                    for (uint32_t j0 = g * per; j0 - g * per < L; j0 += G * per) {
+                        const uint4 q4 = *(const uint4 *)(vals + j0);
+                        uint32_t hits = 0;  // bit q: value j0 + q is a mark
+#pragma unroll
+                        for (uint32_t q = 0; q < per; q++) {
+                            const uint32_t wv = q * W < 4 ? q4.x : q * W < 8 ? q4.y : q * W < 12 ? q4.z : q4.w;
+                            const uint32_t v = W == 4 ? wv : (wv >> (8 * ((q * W) & 3))) & ((1u << (8 * W)) - 1);
+                            hits |= (t && j0 + q < Lb && v == mark) ? 1u << q : 0u;
+                        }
+                        const uint32_t cnt = __popc(hits);
+                        uint32_t pre = 0, tot = 0;
+#pragma unroll
+                        for (int b = 0; b < 5; b++) {  // cnt <= 16
+                            const uint64_t m = __ballot((cnt >> b) & 1) & gmask;
+                            pre += (uint32_t)__popcll(m & below) << b;
+                            tot += (uint32_t)__popcll(m) << b;
+                        }
+                        uint32_t pos = run + pre;
+                        while (hits) {
+                            const uint32_t q = __ffs(hits) - 1;
+                            hits &= hits - 1;
+                            vals[j0 + q] = (V)(mark + excess(pos++));
+                        }
+                        run += tot;
                     }
-                    run += (uint32_t)__popcll(m);
+                } else {
+                    // one value per lane per round (consecutive LDS addresses); a ballot ranks the
+                    // marks of the round
+                    for (uint32_t j = g; j - g < L; j += G) {
+                        const bool hit = t && j < Lb && (uint32_t)vals[j] == mark;
+                        const uint64_t m = __ballot(hit) & gmask;
+                        if (hit) vals[j] = (V)(mark + excess(run + (uint32_t)__popcll(m & below)));
+                        run += (uint32_t)__popcll(m);
+                    }
                 }
             }
         } else {
