@@ -288,10 +288,11 @@ def main():
     value = nbytes / (tc + td) / 1e9
     ratio = nbytes / stream_len
     # Roofline of the decompression kernel: one launch (the pcomp_decompress call is that
-    # kernel plus two width-mismatch launches that return at once), timed live above; its
+    # kernel plus five launches for the other widths and lane-group sizes, which return at once),
+    # timed live above; its
     # algorithmic bytes are the stream it reads plus the values it writes. Compression is a
     # pipeline of launches (statistics, scan, packing) and is reported as a whole beside it.
-    kern = "decompress_kernel<2>"
+    kern = "decompress_kernel<2, false>"
     alg = stream_len + nbytes
     achieved = alg / td / 1e9
     traffic = traffic_from_profiles(kern, alg)

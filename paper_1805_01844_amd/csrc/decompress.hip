@@ -112,7 +112,7 @@ __device__ __forceinline__ void unpack_adv_slow(const DevTables &T, uint64_t bas
 
 // Decodes words i0, i0+G, ... of one part (main digits or excess list) into dst[0 .. n);
 // `add` is added to every digit (the block minimum for plain blocks).
-template <typename V, bool Wide, typename Dst>
+template <typename V, bool Wide, bool kRuns, typename Dst>
 __device__ __forceinline__ void unpack_part(const DevTables &T, const PartBase &pb, uint32_t n, int fam,
                                             uint32_t nwords, uint32_t i0, uint32_t G, const uint64_t *src, Dst dst,
                                             uint32_t add) {
@@ -137,7 +137,9 @@ __device__ __forceinline__ void unpack_part(const DevTables &T, const PartBase &
         if (i < nwords) peel_digits<Wide>(pb, w, i * k, k, put);
         return;
     }
-    if (pb.D) {
+    if (pb.D && !kRuns) {
+        // few lanes per block: lane i0 takes words i0, i0 + G, ... and reads the next word for
+        // the value split at the end of each
         const BaseDesc &D = *pb.D;
         for (uint32_t i = i0; i < nwords; i += G) {
             uint32_t q;
@@ -162,13 +164,46 @@ __device__ __forceinline__ void unpack_part(const DevTables &T, const PartBase &
         }
         return;
     }
+    if (pb.D) {
+        // Lane i0 of the group decodes a run of consecutive words, so the value split between
+        // two of them is rebuilt from what it already has: r_{i-1} from the bottom of word i-1
+        // and r'_{i-1}, the part left on top of word i once its digits are peeled. Only the value
+        // split after the run's last word reads the next word.
+        const BaseDesc &D = *pb.D;
+        const uint32_t run = udiv_small(nwords + G - 1, G);
+        const uint32_t w0 = i0 * run, w1 = w0 + run < nwords ? w0 + run : nwords;
+        uint64_t r_prev = 0, R_prev = 0;  // r_{i-1}, R_{i-1}
+        uint32_t q = 0, p = 0;
+        for (uint32_t i = w0; i < w1; i++) {
+            const AtlasEntry *e = adv_entry(T, D, i, q);
+            const uint64_t X = src[i];
+            const uint64_t qR = div_magic(X, e->mR);
+            const uint64_t r = X - qR * e->R;  // r_i, the low part of the next split value
+            p = e->p;
+            // every word before the block's last holds only values
+            const uint64_t top = i + 1 < nwords ? peel_digits<Wide>(pb, qR, q, p, put_all)
+                                                : peel_digits<Wide>(pb, qR, q, p, put);
+            if (i > w0) put_all(q - 1, (uint32_t)(top * R_prev + r_prev));
+            r_prev = r;
+            R_prev = e->R;
+        }
+        // the value split between the run's last word and the next run's first
+        if (w0 < w1 && w1 < nwords && q + p < n) {
+            uint32_t q1;
+            const AtlasEntry *e1 = adv_entry(T, D, w1, q1);
+            const uint64_t Y = div_magic(src[w1], e1->mR);
+            const uint64_t rp = div_magic(Y, D.mBp[e1->p == D.k ? 1 : 0]);
+            put(q + p, (uint32_t)(rp * R_prev + r_prev));
+        }
+        return;
+    }
     // base outside the tables (u32 data only)
     if (Wide) unpack_adv_slow<V>(T, pb.base, n, nwords, i0, G, src, dst, add);
 }
 
 // Decodes tile `tile` of the stream at `in` (layout lo, pw payload words, fixed class of a
 // single-class stream) into out. Every thread of the workgroup calls it.
-template <int W>
+template <int W, bool kRuns>
 __device__ __forceinline__ void decode_tile(const DevTables &T, const uint8_t *in, const Layout &lo, uint64_t pw,
                                             int fixed, uint64_t tile, uint8_t *out, int32_t *status, DecShared &S) {
     typedef typename Elem<W>::T V;
@@ -257,18 +292,18 @@ __device__ __forceinline__ void decode_tile(const DevTables &T, const uint8_t *i
             const uint64_t *src = payload + S.off[blk];
             V *vals = s_val + (size_t)blk * L;
             if (t == 0) {
-                unpack_part<V, (W == 4)>(T, resolve_base<(W == 4)>(T, S.C, B), Lb, fam, nwb, g, G, src, vals,
+                unpack_part<V, (W == 4), kRuns>(T, resolve_base<(W == 4)>(T, S.C, B), Lb, fam, nwb, g, G, src, vals,
                                          S.min[blk]);
             } else {
                 const uint64_t Th = 1ull << (bitlen64(B - 1) - t);
                 const uint32_t nwm = S.nwm[blk];
-                unpack_part<V, (W == 4)>(T, resolve_base<(W == 4)>(T, S.C, Th + 1), Lb, fam, nwm, g, G, src, vals,
+                unpack_part<V, (W == 4), kRuns>(T, resolve_base<(W == 4)>(T, S.C, Th + 1), Lb, fam, nwm, g, G, src, vals,
                                          S.min[blk]);
                 const PartBase pe = resolve_base<(W == 4)>(T, S.C, B - Th);
                 if (exc_lds)
-                    unpack_part<V, (W == 4)>(T, pe, S.ne[blk], fam, nwb - nwm, g, G, src + nwm, l_exc + S.exoff[blk], 0);
+                    unpack_part<V, (W == 4), kRuns>(T, pe, S.ne[blk], fam, nwb - nwm, g, G, src + nwm, l_exc + S.exoff[blk], 0);
                 else
-                    unpack_part<V, (W == 4)>(T, pe, S.ne[blk], fam, nwb - nwm, g, G, src + nwm, g_exc + S.exoff[blk], 0);
+                    unpack_part<V, (W == 4), kRuns>(T, pe, S.ne[blk], fam, nwb - nwm, g, G, src + nwm, g_exc + S.exoff[blk], 0);
             }
         }
         __syncthreads();
@@ -404,11 +439,14 @@ __device__ __forceinline__ void decode_tile(const DevTables &T, const uint8_t *i
     }
 }
 
-// One kernel per element width (the stream's width is only known on the device): each
-// returns at once unless the header carries its width, so only one does the work.
-// Five wavefronts per SIMD (at most 96 vector registers) fit without spilling for u8 and u16,
-// and five workgroups per CU fit the LDS (under 32 KiB each, with the 8 KiB excess buffer).
-template <int W>
+// Lanes per block from which advanced words are decoded in runs of consecutive words.
+constexpr uint32_t kRunLanes = 8;
+
+// One kernel per element width and lane-group size (both are only known on the device, from
+// the stream's header): each returns at once unless the header matches it, so only one does
+// the work. Five wavefronts per SIMD (at most 96 vector registers) fit for u8 and u16, and five
+// workgroups per CU fit the LDS (under 32 KiB each, with the 8 KiB excess buffer).
+template <int W, bool kRuns>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(W == 4 ? 4 : 5))) void decompress_kernel(
     DecompressArgs a) {
     __shared__ DecShared S;
@@ -416,11 +454,11 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(W == 4
     uint64_t pw;
     int fixed;
     const bool ok = read_layout(a.in, a.in_size, lo, pw, fixed);
-    if (W == 1 && !ok) {  // reported once, by the width-1 kernel
+    if (W == 1 && !kRuns && !ok) {  // reported once, by one kernel
         if (blockIdx.x == 0 && threadIdx.x == 0) set_status(a.status, PCOMP_ECORRUPT);
         return;
     }
-    if (!ok || lo.w != W) return;
+    if (!ok || lo.w != W || (kThreads / lo.tile_blocks >= kRunLanes) != kRuns) return;
     if ((uint64_t)lo.L * lo.w > kTileBytes) {
         if (blockIdx.x == 0 && threadIdx.x == 0) set_status(a.status, PCOMP_EINVAL);
         return;
@@ -432,12 +470,12 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(W == 4
     fill_size_ctx(a.T, lo.L, S.C);
     __syncthreads();
     for (uint64_t tile = blockIdx.x; tile < lo.n_tiles; tile += gridDim.x)
-        decode_tile<W>(a.T, a.in, lo, pw, fixed, tile, a.out, a.status, S);
+        decode_tile<W, kRuns>(a.T, a.in, lo, pw, fixed, tile, a.out, a.status, S);
 }
 
 // Batch: the tiles of one width group, each decoded into its segment's destination. A
 // segment whose stream header disagrees with the plan is reported corrupt and skipped.
-template <int W>
+template <int W, bool kRuns>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(W == 4 ? 4 : 5))) void decompress_batch_kernel(
     BatchDecArgs a) {
     __shared__ DecShared S;
@@ -455,7 +493,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(W == 4
             if (threadIdx.x == 0) set_status(a.status, PCOMP_ECORRUPT);
             continue;
         }
-        decode_tile<W>(a.T, s, lo, pw, fixed, gt - sd.tile0, (uint8_t *)sd.data, a.status, S);
+        decode_tile<W, kRuns>(a.T, s, lo, pw, fixed, gt - sd.tile0, (uint8_t *)sd.data, a.status, S);
     }
 }
 
@@ -474,9 +512,12 @@ int launch_decompress(const void *d_in, size_t in_size, void *d_out, size_t out_
     // persistent grid: enough workgroups to fill every CU several times over
     const uint64_t max_tiles = in_size > kHdrBytes ? (in_size - kHdrBytes) / 8 : 1;
     const uint32_t grid = (uint32_t)(max_tiles < 1 ? 1 : (max_tiles < 4096 ? max_tiles : 4096));
-    decompress_kernel<1><<<grid, kThreads, 0, st>>>(a);
-    decompress_kernel<2><<<grid, kThreads, 0, st>>>(a);
-    decompress_kernel<4><<<grid, kThreads, 0, st>>>(a);
+    decompress_kernel<1, false><<<grid, kThreads, 0, st>>>(a);
+    decompress_kernel<1, true><<<grid, kThreads, 0, st>>>(a);
+    decompress_kernel<2, false><<<grid, kThreads, 0, st>>>(a);
+    decompress_kernel<2, true><<<grid, kThreads, 0, st>>>(a);
+    decompress_kernel<4, false><<<grid, kThreads, 0, st>>>(a);
+    decompress_kernel<4, true><<<grid, kThreads, 0, st>>>(a);
     return hipGetLastError() == hipSuccess ? PCOMP_OK : PCOMP_EHIP;
 }
 
@@ -501,12 +542,19 @@ int launch_decompress_batch(const BatchPlanHeader &ph, const SegDesc *d_segs, co
         b.L = ph.L[g];
         const uint32_t want = grid ? grid : 4096;
         const uint32_t gg = (uint32_t)(ntg < want ? ntg : want);
-        if (g == 0)
-            decompress_batch_kernel<1><<<gg, kThreads, 0, st>>>(b);
+        const bool runs = kThreads / tile_blocks_of(b.L, 1u << g) >= kRunLanes;
+        if (g == 0 && runs)
+            decompress_batch_kernel<1, true><<<gg, kThreads, 0, st>>>(b);
+        else if (g == 0)
+            decompress_batch_kernel<1, false><<<gg, kThreads, 0, st>>>(b);
+        else if (g == 1 && runs)
+            decompress_batch_kernel<2, true><<<gg, kThreads, 0, st>>>(b);
         else if (g == 1)
-            decompress_batch_kernel<2><<<gg, kThreads, 0, st>>>(b);
+            decompress_batch_kernel<2, false><<<gg, kThreads, 0, st>>>(b);
+        else if (runs)
+            decompress_batch_kernel<4, true><<<gg, kThreads, 0, st>>>(b);
         else
-            decompress_batch_kernel<4><<<gg, kThreads, 0, st>>>(b);
+            decompress_batch_kernel<4, false><<<gg, kThreads, 0, st>>>(b);
     }
     return hipGetLastError() == hipSuccess ? PCOMP_OK : PCOMP_EHIP;
 }
