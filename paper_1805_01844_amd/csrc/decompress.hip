@@ -439,9 +439,6 @@ __device__ __forceinline__ void decode_tile(const DevTables &T, const uint8_t *i
     }
 }
 
-// Lanes per block from which advanced words are decoded in runs of consecutive words.
-constexpr uint32_t kRunLanes = 8;
-
 // One kernel per element width and lane-group size (both are only known on the device, from
 // the stream's header): each returns at once unless the header matches it, so only one does
 // the work. Five wavefronts per SIMD (at most 96 vector registers) fit for u8 and u16, and five

@@ -22,6 +22,10 @@ struct Elem<4> {
     typedef uint32_t T;
 };
 
+// Lanes per block from which advanced words are packed and decoded in runs of consecutive
+// words per lane (fewer lanes take every G-th word).
+constexpr uint32_t kRunLanes = 8;
+
 // ---------------------------------------------------------------------------------------
 // Group collectives: G lanes (a power of two, aligned) cooperate on one block. Within a
 // wavefront they use cross-lane shuffles; groups wider than a wavefront combine per-wave
