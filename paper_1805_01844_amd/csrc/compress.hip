@@ -157,7 +157,7 @@ struct ExcessReader {
 // Packs the words of one part of a block (main digits or the excess list); the lanes of
 // the block's group call it with their first word index and stride. get(j) returns digit j
 // of the part, 0 past its end.
-template <bool Wide, bool kRuns, typename Get>
+template <bool Wide, typename Get>
 __device__ __forceinline__ void pack_part(const DevTables &T, const SizeCtx &C, uint64_t base, uint32_t n, int fam,
                                           uint32_t nwords, uint32_t i0, uint32_t G, uint64_t *dst, Get get) {
     if (nwords == 0 || i0 >= nwords) return;
@@ -167,10 +167,11 @@ __device__ __forceinline__ void pack_part(const DevTables &T, const SizeCtx &C, 
         for (uint32_t i = i0; i < nwords; i += G) dst[i] = horner_digits<Wide>(pb, 0, i * pb.k, pb.k, get);
         return;
     }
-    if (pb.D && kRuns) {
-        // Sec. 3.2 series, lane i0 of the group packing a run of consecutive words: one division
-        // of the value split between two words gives both r_i (its remainder by R_i, at the
-        // bottom of word i) and r'_i (the quotient, on top of word i + 1)
+    if (pb.D) {
+        // Sec. 3.2 series: word i = (r'_{i-1} B^{p_i} + digits) R_i + r_i, state from the cycle
+        // form. Lane i0 of the group packs a run of consecutive words: one division of the value
+        // split between two words gives both r_i (its remainder by R_i, at the bottom of word i)
+        // and r'_i (the quotient, on top of word i + 1).
         const BaseDesc &D = *pb.D;
         const uint32_t run = udiv_small(nwords + G - 1, G);
         const uint32_t w0 = i0 * run, w1 = w0 + run < nwords ? w0 + run : nwords;
@@ -191,26 +192,6 @@ __device__ __forceinline__ void pack_part(const DevTables &T, const SizeCtx &C, 
             const uint64_t qx = div_magic(x, e->mR);
             dst[i] = acc * e->R + (x - qx * e->R);
             rp = qx;
-        }
-        return;
-    }
-    if (pb.D) {
-        // Sec. 3.2 series: word i = (r'_{i-1} B^{p_i} + digits) R_i + r_i, state from the cycle form
-        const BaseDesc &D = *pb.D;
-        for (uint32_t i = i0; i < nwords; i += G) {
-            uint32_t q;
-            const AtlasEntry *e = adv_entry(T, D, i, q);
-            uint32_t rp = 0;  // r'_{i-1}: top part of the value split at the end of word i-1
-            if (i > 0) {
-                uint32_t qp;
-                const AtlasEntry *ep = adv_entry(T, D, i - 1, qp);
-                rp = (uint32_t)div_magic(get(q - 1), ep->mR);
-            }
-            // digits are read in increasing order (the excess-list reader relies on it)
-            const uint64_t acc = horner_digits<Wide>(pb, rp, q, e->p, get);
-            const uint64_t x = get(q + e->p);
-            const uint64_t r = x - div_magic(x, e->mR) * e->R;
-            dst[i] = acc * e->R + r;
         }
         return;
     }
@@ -603,7 +584,7 @@ __global__ __launch_bounds__(kThreads) void scan_prefix_kernel(CompressArgs a, c
 }
 
 // ---- launch 4: packing ----------------------------------------------------------------
-template <int W, bool kPersist, bool kRuns>
+template <int W, bool kPersist>
 __global__ __launch_bounds__(kThreads) void pack_kernel(CompressArgs a) {
     typedef typename Elem<W>::T V;
     __shared__ uint4 s_raw[kTileBytes / 16 + 1];
@@ -740,21 +721,21 @@ __global__ __launch_bounds__(kThreads) void pack_kernel(CompressArgs a) {
         if (live && nw) {
             uint64_t *dst = (uint64_t *)(so + lo.off_payload) + base_off + s_off[blk];
             if (tcls == 0) {
-                pack_part<(W == 4), kRuns>(T, s_C, B, Lb, fam, nw, g, G, dst,
+                pack_part<(W == 4)>(T, s_C, B, Lb, fam, nw, g, G, dst,
                           [&](uint32_t j) -> uint64_t { return j < Lb ? (uint64_t)((uint32_t)bv[j] - bmin) : 0; });
             } else {
-                pack_part<(W == 4), kRuns>(T, s_C, Th + 1, Lb, fam, nwm, g, G, dst, [&](uint32_t j) -> uint64_t {
+                pack_part<(W == 4)>(T, s_C, Th + 1, Lb, fam, nwm, g, G, dst, [&](uint32_t j) -> uint64_t {
                     if (j >= Lb) return 0;
                     const uint64_t d = (uint32_t)bv[j] - bmin;
                     return d < Th ? d : Th;
                 });
                 if (compact) {
                     const V *ex = s_ex + s_exoff[blk];
-                    pack_part<(W == 4), kRuns>(T, s_C, B - Th, ne, fam, nw - nwm, g, G, dst + nwm,
+                    pack_part<(W == 4)>(T, s_C, B - Th, ne, fam, nw - nwm, g, G, dst + nwm,
                                         [&](uint32_t j) -> uint64_t { return j < ne ? (uint64_t)ex[j] : 0; });
                 } else {
                     ExcessReader<V> exr{bv, s_cpre + (tid - g), Lb, ch, G, ne, bmin, (uint32_t)Th, 0, 0, 0};
-                    pack_part<(W == 4), kRuns>(T, s_C, B - Th, ne, fam, nw - nwm, g, G, dst + nwm,
+                    pack_part<(W == 4)>(T, s_C, B - Th, ne, fam, nw - nwm, g, G, dst + nwm,
                                         [&](uint32_t j) -> uint64_t { return exr(j); });
                 }
             }
@@ -800,8 +781,7 @@ uint64_t compress_ws_bytes(uint64_t n_tiles) {
 // One per-tile launch (stats or pack) of width W; a persistent grid walks the tiles with a
 // stride, otherwise every workgroup takes one tile (the kernel then holds fewer registers).
 template <int W>
-void launch_tiles(bool stats, bool persist, bool word_runs, uint32_t grid, size_t dyn, const CompressArgs &b,
-                  hipStream_t st) {
+void launch_tiles(bool stats, bool persist, uint32_t grid, size_t dyn, const CompressArgs &b, hipStream_t st) {
     const bool learned = b.variant == PCOMP_SELECT_LEARNED;
     if (stats && learned) {
         if (persist)
@@ -813,14 +793,10 @@ void launch_tiles(bool stats, bool persist, bool word_runs, uint32_t grid, size_
             stats_kernel<W, true, false><<<grid, kThreads, 0, st>>>(b);
         else
             stats_kernel<W, false, false><<<grid, kThreads, 0, st>>>(b);
-    } else if (persist && word_runs) {
-        pack_kernel<W, true, true><<<grid, kThreads, dyn, st>>>(b);
     } else if (persist) {
-        pack_kernel<W, true, false><<<grid, kThreads, dyn, st>>>(b);
-    } else if (word_runs) {
-        pack_kernel<W, false, true><<<grid, kThreads, dyn, st>>>(b);
+        pack_kernel<W, true><<<grid, kThreads, dyn, st>>>(b);
     } else {
-        pack_kernel<W, false, false><<<grid, kThreads, dyn, st>>>(b);
+        pack_kernel<W, false><<<grid, kThreads, dyn, st>>>(b);
     }
 }
 
@@ -869,11 +845,11 @@ int launch_compress_table(const SegDesc *segs, const uint32_t *tile_seg, const S
         const bool persist = grid && grid < ntg;
         const uint32_t gg = (uint32_t)(persist ? grid : ntg);
         if (g == 0)
-            launch_tiles<1>(true, persist, false, gg, 0, b, st);
+            launch_tiles<1>(true, persist, gg, 0, b, st);
         else if (g == 1)
-            launch_tiles<2>(true, persist, false, gg, 0, b, st);
+            launch_tiles<2>(true, persist, gg, 0, b, st);
         else
-            launch_tiles<4>(true, persist, false, gg, 0, b, st);
+            launch_tiles<4>(true, persist, gg, 0, b, st);
     }
     const uint32_t runs = (uint32_t)((n_tiles + kScanTiles - 1) / kScanTiles);
     if (runs > 0) {
@@ -889,13 +865,12 @@ int launch_compress_table(const SegDesc *segs, const uint32_t *tile_seg, const S
         b.ctx = ctx + g;
         const bool persist = grid && grid < ntg;
         const uint32_t gg = (uint32_t)(persist ? grid : ntg);
-        const bool word_runs = kThreads / tile_blocks_of(L[g], 1u << g) >= kRunLanes;
         if (g == 0)
-            launch_tiles<1>(false, persist, word_runs, gg, dyn, b, st);
+            launch_tiles<1>(false, persist, gg, dyn, b, st);
         else if (g == 1)
-            launch_tiles<2>(false, persist, word_runs, gg, dyn, b, st);
+            launch_tiles<2>(false, persist, gg, dyn, b, st);
         else
-            launch_tiles<4>(false, persist, word_runs, gg, dyn, b, st);
+            launch_tiles<4>(false, persist, gg, dyn, b, st);
     }
     return hipGetLastError() == hipSuccess ? PCOMP_OK : PCOMP_EHIP;
 }

@@ -22,8 +22,8 @@ struct Elem<4> {
     typedef uint32_t T;
 };
 
-// Lanes per block from which advanced words are packed and decoded in runs of consecutive
-// words per lane (fewer lanes take every G-th word).
+// Lanes per block from which advanced words are decoded in runs of consecutive words per lane
+// (fewer lanes take every G-th word; packing always uses runs).
 constexpr uint32_t kRunLanes = 8;
 
 // ---------------------------------------------------------------------------------------
