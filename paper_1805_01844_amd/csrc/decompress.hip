@@ -172,7 +172,7 @@ __device__ __forceinline__ void unpack_part(const DevTables &T, const PartBase &
         const BaseDesc &D = *pb.D;
         const uint32_t run = udiv_small(nwords + G - 1, G);
         const uint32_t w0 = i0 * run, w1 = w0 + run < nwords ? w0 + run : nwords;
-        uint64_t r_prev = 0, R_prev = 0;  // r_{i-1}, R_{i-1}
+        uint32_t r_prev = 0, R_prev = 0;  // r_{i-1} < R_{i-1} <= B
         uint32_t q = 0, p = 0;
         for (uint32_t i = w0; i < w1; i++) {
             const AtlasEntry *e = adv_entry(T, D, i, q);
@@ -184,7 +184,7 @@ __device__ __forceinline__ void unpack_part(const DevTables &T, const PartBase &
             const uint64_t top = i + 1 < nwords ? peel_digits<Wide>(pb, qR, q, p, put_all)
                                                 : peel_digits<Wide>(pb, qR, q, p, put);
             if (i > w0) put_all(q - 1, (uint32_t)(top * R_prev + r_prev));
-            r_prev = r;
+            r_prev = (uint32_t)r;
             R_prev = e->R;
         }
         // the value split between the run's last word and the next run's first
