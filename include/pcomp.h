@@ -97,8 +97,9 @@ int pcomp_init(void);
 size_t pcomp_bound(uint64_t n, pcomp_dtype dtype, uint32_t block_len, int variant);
 
 /* Host-only, pure. Device workspace bytes that pcomp_compress needs (an error
- * word, size tables, per-tile word totals and their prefix sums). Returns 0
- * for invalid args. */
+ * word, size tables, three tables of advanced word counts for full blocks
+ * (128 KiB each), per-tile word totals and their prefix sums). Returns 0 for
+ * invalid args. */
 size_t pcomp_workspace_size(uint64_t n, pcomp_dtype dtype, uint32_t block_len, int variant);
 
 /* Compresses n values of `dtype` at d_in (any alignment of the element type)
