@@ -230,7 +230,7 @@ def main():
         print(json.dumps({"copy_bytes": 1 << 30, "copies": 3}), flush=True)
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build runs on a single MI355X (--gpus 1).", file=sys.stderr)
+        print("bench.py measures one GPU only: the library runs on a single MI355X (--gpus 1).", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
