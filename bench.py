@@ -261,7 +261,7 @@ def main():
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(3 * (args.steps + args.warmup))]
     for i in range(args.warmup):
         comp(xf)
-        pc.decompress_into(stream, out, status)
+        pc.decompress_into(stream, out, status, dtype_bytes=2)
     torch.cuda.synchronize()
     t_c, t_d = [], []
     wall0 = time.perf_counter()
@@ -270,7 +270,7 @@ def main():
         e0.record()
         comp(xf)
         e1.record()
-        pc.decompress_into(stream, out, status)
+        pc.decompress_into(stream, out, status, dtype_bytes=2)
         e2.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0

@@ -93,6 +93,16 @@ def _check(rc, what):
         raise PcompError(rc, what)
 
 
+def _require(cond, what):
+    """Argument checks of the binding (kept under ``python -O``, unlike assert)."""
+    if not cond:
+        raise ValueError(what)
+
+
+def _is_values(t: torch.Tensor) -> bool:
+    return t.is_cuda and t.is_contiguous() and t.dtype in _DT
+
+
 def init() -> None:
     _check(lib().pcomp_init(), "pcomp_init")
 
@@ -120,7 +130,8 @@ class Compressor:
 
     def __call__(self, x: torch.Tensor) -> None:
         """Enqueues compression of x on the current stream (asynchronous)."""
-        assert x.is_cuda and x.numel() == self.n and _DT[x.dtype] == self.w and x.is_contiguous()
+        _require(_is_values(x) and x.numel() == self.n and _DT[x.dtype] == self.w and x.device == self.out.device,
+                 "x is a contiguous CUDA tensor of the compressor's size, dtype and device")
         rc = lib().pcomp_compress(ctypes.c_void_p(x.data_ptr()), self.n, self.w, self.L, self.variant,
                                   ctypes.c_void_p(self.out.data_ptr()), self.out.numel(),
                                   ctypes.c_void_p(self.size.data_ptr()), ctypes.c_void_p(self.ws.data_ptr()),
@@ -160,8 +171,19 @@ def stream_info(stream: torch.Tensor):
     return n.value, w.value, L.value, tot.value
 
 
-def decompress_into(stream: torch.Tensor, out: torch.Tensor, status: torch.Tensor) -> None:
-    """Enqueues decompression into `out` on the current stream (asynchronous); status is i32[1]."""
+def decompress_into(stream: torch.Tensor, out: torch.Tensor, status: torch.Tensor, dtype_bytes: int = None) -> None:
+    """Enqueues decompression into `out` on the current stream (asynchronous); status is i32[1].
+
+    `out` must have the stream's dtype: the library takes its capacity in values of that dtype.
+    Without `dtype_bytes` the header is read to check it (a 64-byte copy that synchronises);
+    a caller that already knows the stream's element size (from ``stream_info``) passes it."""
+    _require(stream.is_cuda and stream.dtype == torch.uint8 and stream.is_contiguous(),
+             "stream is a contiguous u8 CUDA tensor")
+    _require(_is_values(out), "out is a contiguous u8/u16/u32 CUDA tensor")
+    _require(status.is_cuda and status.dtype == torch.int32 and status.numel() >= 1, "status is an i32 CUDA tensor")
+    _require(stream.device == out.device == status.device, "stream, out and status are on one device")
+    w = stream_info(stream)[1] if dtype_bytes is None else int(dtype_bytes)
+    _require(_DT[out.dtype] == w, "out has the stream's dtype (%d bytes per value)" % w)
     rc = lib().pcomp_decompress(ctypes.c_void_p(stream.data_ptr()), stream.numel(), ctypes.c_void_p(out.data_ptr()),
                                 out.numel(), ctypes.c_void_p(status.data_ptr()), _stream_handle())
     _check(rc, "pcomp_decompress")
@@ -171,7 +193,7 @@ def decompress(stream: torch.Tensor) -> torch.Tensor:
     n, w, L, tot = stream_info(stream)
     out = torch.empty(max(n, 1), dtype=_TORCH[w], device=stream.device)
     status = torch.zeros(1, dtype=torch.int32, device=stream.device)
-    decompress_into(stream, out, status)
+    decompress_into(stream, out, status, dtype_bytes=w)
     st = int(status.item())
     if st != OK:
         raise PcompError(st, "pcomp_decompress (device status)")
@@ -204,7 +226,7 @@ def _block_lens(block_len):
     if isinstance(block_len, int):
         return (block_len, block_len, block_len)
     bl = tuple(int(x) for x in block_len)
-    assert len(bl) == 3
+    _require(len(bl) == 3, "block_len is an int or one length per width group (u8, u16, u32)")
     return bl
 
 
@@ -213,7 +235,7 @@ class _Plan:
 
     def __init__(self, tensors, block_len, variant, device):
         for t in tensors:
-            assert t.is_cuda and t.is_contiguous() and t.dtype in _DT, "segments are contiguous u8/u16/u32 CUDA tensors"
+            _require(_is_values(t), "segments are contiguous u8/u16/u32 CUDA tensors")
         self.n_segs = len(tensors)
         self.segs = (_Segment * max(1, self.n_segs))()
         for i, t in enumerate(tensors):
@@ -294,16 +316,17 @@ class BatchDecoder:
     """Decompression of a Batch's buffer into destination tensors shaped like its segments."""
 
     def __init__(self, batch: Batch, outs, grid=0):
-        assert len(outs) == len(batch.tensors)
+        _require(len(outs) == len(batch.tensors), "one destination per segment")
         for t, o in zip(batch.tensors, outs):
-            assert o.numel() == t.numel() and o.dtype == t.dtype
+            _require(o.numel() == t.numel() and o.dtype == t.dtype, "destinations are shaped like the segments")
         self.batch, self.outs, self.grid = batch, list(outs), int(grid)
         self.plan = _Plan(self.outs, batch.block_len, batch.variant, batch.out.device)
-        assert self.plan.offsets == batch.plan.offsets
+        _require(self.plan.offsets == batch.plan.offsets, "destination plan matches the batch's")
         self.status = torch.zeros(1, dtype=torch.int32, device=batch.out.device)
 
     def __call__(self, buf: torch.Tensor = None) -> None:
         buf = self.batch.out if buf is None else buf
+        _require(buf.is_cuda and buf.dtype == torch.uint8 and buf.is_contiguous(), "buf is a contiguous u8 CUDA tensor")
         rc = lib().pcomp_decompress_batch(self.plan.host, ctypes.c_void_p(self.plan.device.data_ptr()),
                                           ctypes.c_void_p(buf.data_ptr()), buf.numel(),
                                           ctypes.c_void_p(self.status.data_ptr()), self.grid, _stream_handle())
@@ -338,6 +361,7 @@ def set_model(params) -> None:
 def block_features(x: torch.Tensor, block_len: int, want_x=True, want_words=True, want_label=True):
     """(features [nb, 19] f32, class words [nb, 16] u32-as-int32, labels [nb] u8) of a CUDA
     array, computed on the GPU; entries not wanted are None."""
+    _require(x.is_cuda and x.dtype in _DT, "x is a u8/u16/u32 CUDA tensor")
     x = x.contiguous().reshape(-1)
     n, w = x.numel(), _DT[x.dtype]
     nb = (n + block_len - 1) // block_len
@@ -353,7 +377,16 @@ def block_features(x: torch.Tensor, block_len: int, want_x=True, want_words=True
     return cut(fx), cut(words), cut(lab)
 
 
+def _require_mlp_inputs(params: torch.Tensor, X: torch.Tensor):
+    _require(params.is_cuda and params.dtype == torch.float32 and params.is_contiguous() and
+             params.numel() == MLP_PARAMS, "params is a contiguous f32 CUDA tensor of %d values" % MLP_PARAMS)
+    _require(X.is_cuda and X.dtype == torch.float32 and X.is_contiguous() and X.dim() == 2 and
+             X.shape[1] == MLP_IN and X.device == params.device,
+             "X is a contiguous f32 [n, %d] tensor on the device of params" % MLP_IN)
+
+
 def mlp_scores(params: torch.Tensor, X: torch.Tensor) -> torch.Tensor:
+    _require_mlp_inputs(params, X)
     n = X.shape[0]
     S = torch.empty((max(n, 1), MLP_OUT), dtype=torch.float32, device=X.device)
     _check(lib().pcomp_mlp_scores(_vp(params), _vp(X), n, _vp(S), _stream_handle()), "pcomp_mlp_scores")
@@ -374,8 +407,11 @@ class MLPTrainer:
         self.max_batch, self.lr, self.betas, self.eps, self.step_no = max_batch, lr, betas, eps, 0
 
     def loss_grad(self, X: torch.Tensor, y: torch.Tensor) -> None:
+        _require_mlp_inputs(self.params, X)
         n = X.shape[0]
-        assert 0 < n <= self.max_batch and X.is_contiguous() and y.dtype == torch.uint8
+        _require(0 < n <= self.max_batch, "1 <= batch <= max_batch")
+        _require(y.device == X.device and y.dtype == torch.uint8 and y.is_contiguous() and y.numel() >= n,
+                 "y holds one u8 label per row of X, on its device")
         rc = lib().pcomp_mlp_loss_grad(_vp(self.params), _vp(X), _vp(y), n, _vp(self.grad), _vp(self.loss),
                                        _vp(self.ws), self.ws.numel(), _stream_handle())
         _check(rc, "pcomp_mlp_loss_grad")

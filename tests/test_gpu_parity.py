@@ -149,3 +149,20 @@ def test_dense_excess_lists(pc, orc, variant):
         x = torch.randint(0, hi, (7 * L + 13,), generator=g, dtype=torch.int64)
         x = x.to(torch.int32).to(dt) if dt != torch.uint8 else x.to(dt)
         _check(pc, orc, x, L, variant, "dense_excess")
+
+
+def test_decompress_into_checks_the_output_dtype(pc):
+    """The library counts the output capacity in values of the stream's dtype, so an output of
+    another dtype is refused by the binding instead of being written past its end."""
+    x = torch.arange(5000, dtype=torch.int32).to(torch.uint16).cuda()
+    st = pc.compress(x, 40)
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    with pytest.raises(ValueError):
+        pc.decompress_into(st, torch.empty(x.numel(), dtype=torch.uint8, device="cuda"), status)
+    with pytest.raises(ValueError):
+        pc.decompress_into(st, torch.empty(x.numel(), dtype=torch.uint8, device="cuda"), status, dtype_bytes=2)
+    out = torch.empty_like(x)
+    pc.decompress_into(st, out, status)
+    assert int(status.item()) == 0 and torch.equal(out.view(torch.int16), x.view(torch.int16))
+    with pytest.raises(ValueError):
+        pc.mlp_scores(torch.zeros(pc.MLP_PARAMS, device="cuda"), torch.zeros(4, pc.MLP_IN - 1, device="cuda"))

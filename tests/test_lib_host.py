@@ -141,3 +141,19 @@ def test_batch_plan_rejects_bad_arguments(pc):
     assert pc.lib().pcomp_batch_plan_bytes(_segs(pc, [(1, 10)]), 1, big, 0) > 0
     buf = (ctypes.c_uint64 * 8)()
     assert pc.lib().pcomp_batch_info(buf, None, None, None, None) == pc.EINVAL  # not a plan
+
+
+def test_binding_rejects_host_tensors_and_bad_shapes(pc):
+    """The binding refuses arguments the library cannot take before any call reaches it."""
+    import torch
+
+    u8, u16 = torch.zeros(64, dtype=torch.uint8), torch.zeros(8, dtype=torch.uint16)
+    i32 = torch.zeros(1, dtype=torch.int32)
+    with pytest.raises(ValueError):
+        pc.decompress_into(u8, u16, i32)  # host tensors
+    with pytest.raises(ValueError):
+        pc.block_features(u16, 40)
+    with pytest.raises(ValueError):
+        pc.mlp_scores(torch.zeros(pc.MLP_PARAMS), torch.zeros(4, pc.MLP_IN))
+    with pytest.raises(ValueError):
+        pc._block_lens((40, 40))
