@@ -98,8 +98,9 @@ size_t pcomp_bound(uint64_t n, pcomp_dtype dtype, uint32_t block_len, int varian
 
 /* Host-only, pure. Device workspace bytes that pcomp_compress needs (an error
  * word, size tables, three tables of advanced word counts for full blocks
- * (128 KiB each), per-tile word totals and their prefix sums). Returns 0 for
- * invalid args. */
+ * (128 KiB each), per-tile word totals and their prefix sums, and one record
+ * of 2 w + 4 bytes per block: min, B - 1, class, words and n_e, passed from
+ * the sizing launch to the packing launch). Returns 0 for invalid args. */
 size_t pcomp_workspace_size(uint64_t n, pcomp_dtype dtype, uint32_t block_len, int variant);
 
 /* Compresses n values of `dtype` at d_in (any alignment of the element type)
@@ -107,7 +108,12 @@ size_t pcomp_workspace_size(uint64_t n, pcomp_dtype dtype, uint32_t block_len, i
  * stream at d_out (8-byte aligned, out_capacity >= pcomp_bound). The stream
  * size in bytes is written to *d_out_size (device u64). d_ws must hold
  * pcomp_workspace_size bytes and be 8-byte aligned; its contents are
- * overwritten. Calls sharing a workspace must be ordered on one stream. */
+ * overwritten. Calls sharing a workspace must be ordered on one stream.
+ * Error word: after the call, the first u32 of d_ws is 0, or has bit 1 set
+ * when a block's chosen size exceeded its bound (then clamped, and the stream
+ * is not valid) or bit 2 set when a tile's payload offset exceeded the bound
+ * (that tile was not written). Neither happens unless the library itself is
+ * wrong; a caller that wants the check reads the word after the stream. */
 int pcomp_compress(const void *d_in, uint64_t n, pcomp_dtype dtype, uint32_t block_len, int variant,
                    void *d_out, size_t out_capacity, uint64_t *d_out_size, void *d_ws, size_t ws_bytes,
                    void *stream);
@@ -118,6 +124,46 @@ int pcomp_compress(const void *d_in, uint64_t n, pcomp_dtype dtype, uint32_t blo
  * the output is unspecified. No workspace is needed. */
 int pcomp_decompress(const void *d_in, size_t in_size, void *d_out, size_t out_capacity, int32_t *d_status,
                      void *stream);
+
+/* pcomp_decompress for a caller that knows the stream's element type and block
+ * length (those of its compression): only the kernel for them is launched, and
+ * a stream of another type or block length is reported PCOMP_ECORRUPT in
+ * *d_status. Otherwise as pcomp_decompress. */
+int pcomp_decompress_typed(const void *d_in, size_t in_size, pcomp_dtype dtype, uint32_t block_len, void *d_out,
+                           size_t out_capacity, int32_t *d_status, void *stream);
+
+/* ---- Time-major blocking (Sec. 4.3.1) --------------------------------------
+ * The paper lays camera data out as the matrix M whose element M_ij is the
+ * i-th time sample of pixel j, so that a block runs along one time sample
+ * across pixels instead of along one pixel's trace. An event stored pixel by
+ * pixel ([pixels][samples], row-major) is the transpose of M; these calls read
+ * (and write) such matrices column by column without a transposed copy.
+ * pcomp_compress_transposed compresses n_mat row-major matrices [rows][cols]
+ * at d_in as the stream of their transposes: value t of the stream is element
+ * (e, r, c) with t = (e cols + c) rows + r, and the stream is byte for byte
+ * pcomp_compress of the transposed array. Other arguments as pcomp_compress;
+ * rows = 0 or cols = 0 is PCOMP_EINVAL. */
+int pcomp_compress_transposed(const void *d_in, uint64_t n_mat, uint32_t rows, uint32_t cols, pcomp_dtype dtype,
+                              uint32_t block_len, int variant, void *d_out, size_t out_capacity,
+                              uint64_t *d_out_size, void *d_ws, size_t ws_bytes, void *stream);
+
+/* Decompresses such a stream (element type and block length as compressed) back
+ * into n_mat matrices [rows][cols] at d_out (out_capacity values). A stream of
+ * another length, type or block length gives PCOMP_ECORRUPT in *d_status. */
+int pcomp_decompress_transposed(const void *d_in, size_t in_size, pcomp_dtype dtype, uint32_t block_len,
+                                uint64_t n_mat, uint32_t rows, uint32_t cols, void *d_out, size_t out_capacity,
+                                int32_t *d_status, void *stream);
+
+/* ---- Integrated signal (Sec. 4.3.2) ----------------------------------------
+ * The paper's second data set holds, per pixel and event, the integral of the
+ * pixel's waveform (24/32-bit values) rather than its samples. This call makes
+ * such vectors on the GPU: d_out[i] (device u32) = the sum of trace i of
+ * d_in, n_traces traces of `samples` values each, one after another (a camera
+ * event [pixels][samples] gives one sum per pixel). Requires samples *
+ * (largest value of dtype) < 2^32 and samples * dtype bytes <= 16384
+ * (PCOMP_EINVAL otherwise). The sums can then be compressed as u32 data. */
+int pcomp_integrate(const void *d_in, pcomp_dtype dtype, uint64_t n_traces, uint32_t samples, uint32_t *d_out,
+                    void *stream);
 
 /* Host-only: reads n, dtype bytes and total stream size from a header that is
  * already in host memory (first 64 bytes of a stream). Returns PCOMP_OK or
@@ -131,8 +177,11 @@ int pcomp_stream_info(const void *h_header, uint64_t *n, int *dtype_bytes, uint3
  * whole batch. Blocks never cross segments (the method blocks each array on its
  * own, Sec. 3.3); every segment becomes its own v1 stream, exactly the stream
  * pcomp_compress would write for it alone with the same block length and
- * variant. Streams sit in the batch buffer in the caller's order, each in a
- * slot of its pcomp_bound, at offsets the plan fixes.
+ * variant. The streams are written one after another, in the caller's order,
+ * with no gap: the batch buffer's first *d_total bytes are a file that can be
+ * read back by parts (one stream per segment, each with its tile index,
+ * Sec. 3.3 and Sec. 4.3). Where each stream starts is found on the device once
+ * every block is sized, and written to d_seg_offsets.
  *
  * A plan is built on the host from the segment list and must then be copied,
  * byte for byte, to device memory by the caller (8-byte aligned); calls take
@@ -160,27 +209,31 @@ size_t pcomp_batch_plan_bytes(const pcomp_segment *h_segs, uint32_t n_segs, cons
 int pcomp_batch_plan(const pcomp_segment *h_segs, uint32_t n_segs, const uint32_t *block_len, int variant,
                      void *h_plan, size_t plan_bytes);
 
-/* Host-only. From a host plan: batch buffer bytes, workspace bytes, tile
- * count, and (if h_offsets is not NULL) the byte offset of every segment's
- * stream, in the caller's order (n_segs entries). */
-int pcomp_batch_info(const void *h_plan, uint64_t *out_bytes, uint64_t *ws_bytes, uint64_t *n_tiles,
-                     uint64_t *h_offsets);
+/* Host-only. From a host plan: the output capacity a compression needs (the
+ * sum of the segments' pcomp_bound: the streams never take more), the
+ * workspace bytes and the tile count. Any pointer may be NULL. */
+int pcomp_batch_info(const void *h_plan, uint64_t *out_capacity, uint64_t *ws_bytes, uint64_t *n_tiles);
 
-/* Compresses every segment of the plan into d_out (out_capacity >= the plan's
- * buffer bytes); the stream size of segment i goes to d_sizes[i] (device u64).
- * grid = 0 runs the per-tile launches with one workgroup per tile; grid > 0
- * makes them persistent with that many workgroups per width group. The
- * workspace rules of pcomp_compress apply. */
+/* Compresses every segment of the plan into d_out (8-byte aligned,
+ * out_capacity >= the plan's output capacity). Segment i's stream starts at
+ * byte d_seg_offsets[i] (device u64 array of n_segs, caller's order; every
+ * offset is a multiple of 8) and ends where the next one starts; *d_total
+ * (device u64) receives the bytes of all streams together. grid = 0 runs the
+ * per-tile launches with one workgroup per tile; grid > 0 makes them
+ * persistent with that many workgroups per width group. The workspace rules of
+ * pcomp_compress apply, including its error word. */
 int pcomp_compress_batch(const void *h_plan, const void *d_plan, void *d_out, size_t out_capacity,
-                         uint64_t *d_sizes, void *d_ws, size_t ws_bytes, uint32_t grid, void *stream);
+                         uint64_t *d_seg_offsets, uint64_t *d_total, void *d_ws, size_t ws_bytes, uint32_t grid,
+                         void *stream);
 
-/* Decompresses the streams of a batch buffer (in_size bytes at d_in, streams
- * at the plan's offsets) into the plan's segment pointers. *d_status gets
- * PCOMP_OK or PCOMP_ECORRUPT (a header disagrees with the plan, or a stream is
- * inconsistent). grid = 0 picks min(tiles, 4096) workgroups per width group.
- * No workspace is needed. */
+/* Decompresses the streams of a batch buffer (in_size bytes at d_in, segment
+ * i's stream at byte d_seg_offsets[i], device array in the caller's order, as
+ * pcomp_compress_batch wrote it) into the plan's segment pointers. *d_status
+ * gets PCOMP_OK or PCOMP_ECORRUPT (an offset is unaligned or out of range, a
+ * header disagrees with the plan, or a stream is inconsistent). grid = 0 picks
+ * min(tiles, 4096) workgroups per width group. No workspace is needed. */
 int pcomp_decompress_batch(const void *h_plan, const void *d_plan, const void *d_in, size_t in_size,
-                           int32_t *d_status, uint32_t grid, void *stream);
+                           const uint64_t *d_seg_offsets, int32_t *d_status, uint32_t grid, void *stream);
 
 /* ---- Learned class selector ----------------------------------------------------
  * The method leaves the choice of packing to the user (basic or advanced, Sec. 3.1-3.2;

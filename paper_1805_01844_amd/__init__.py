@@ -51,6 +51,14 @@ def lib():
         L.pcomp_compress.argtypes = [vp, u64, i32, u32, i32, vp, sz, vp, vp, sz, vp]
         L.pcomp_decompress.restype = i32
         L.pcomp_decompress.argtypes = [vp, sz, vp, sz, vp, vp]
+        L.pcomp_decompress_typed.restype = i32
+        L.pcomp_decompress_typed.argtypes = [vp, sz, i32, u32, vp, sz, vp, vp]
+        L.pcomp_integrate.restype = i32
+        L.pcomp_integrate.argtypes = [vp, i32, u64, u32, vp, vp]
+        L.pcomp_compress_transposed.restype = i32
+        L.pcomp_compress_transposed.argtypes = [vp, u64, u32, u32, i32, u32, i32, vp, sz, vp, vp, sz, vp]
+        L.pcomp_decompress_transposed.restype = i32
+        L.pcomp_decompress_transposed.argtypes = [vp, sz, i32, u32, u64, u32, u32, vp, sz, vp, vp]
         L.pcomp_stream_info.restype = i32
         L.pcomp_stream_info.argtypes = [vp, vp, vp, vp, vp]
         L.pcomp_atlas_info.restype = i32
@@ -62,11 +70,11 @@ def lib():
         L.pcomp_batch_plan.restype = i32
         L.pcomp_batch_plan.argtypes = [vp, u32, vp, i32, vp, sz]
         L.pcomp_batch_info.restype = i32
-        L.pcomp_batch_info.argtypes = [vp, vp, vp, vp, vp]
+        L.pcomp_batch_info.argtypes = [vp, vp, vp, vp]
         L.pcomp_compress_batch.restype = i32
-        L.pcomp_compress_batch.argtypes = [vp, vp, vp, sz, vp, vp, sz, u32, vp]
+        L.pcomp_compress_batch.argtypes = [vp, vp, vp, sz, vp, vp, vp, sz, u32, vp]
         L.pcomp_decompress_batch.restype = i32
-        L.pcomp_decompress_batch.argtypes = [vp, vp, vp, sz, vp, u32, vp]
+        L.pcomp_decompress_batch.argtypes = [vp, vp, vp, sz, vp, vp, u32, vp]
         L.pcomp_set_model.restype = i32
         L.pcomp_set_model.argtypes = [vp, sz]
         L.pcomp_block_features.restype = i32
@@ -171,19 +179,32 @@ def stream_info(stream: torch.Tensor):
     return n.value, w.value, L.value, tot.value
 
 
-def decompress_into(stream: torch.Tensor, out: torch.Tensor, status: torch.Tensor, dtype_bytes: int = None) -> None:
-    """Enqueues decompression into `out` on the current stream (asynchronous); status is i32[1].
-
-    `out` must have the stream's dtype: the library takes its capacity in values of that dtype.
-    Without `dtype_bytes` the header is read to check it (a 64-byte copy that synchronises);
-    a caller that already knows the stream's element size (from ``stream_info``) passes it."""
+def _check_decode_args(stream, out, status):
     _require(stream.is_cuda and stream.dtype == torch.uint8 and stream.is_contiguous(),
              "stream is a contiguous u8 CUDA tensor")
     _require(_is_values(out), "out is a contiguous u8/u16/u32 CUDA tensor")
     _require(status.is_cuda and status.dtype == torch.int32 and status.numel() >= 1, "status is an i32 CUDA tensor")
     _require(stream.device == out.device == status.device, "stream, out and status are on one device")
+
+
+def decompress_into(stream: torch.Tensor, out: torch.Tensor, status: torch.Tensor, dtype_bytes: int = None,
+                    block_len: int = None) -> None:
+    """Enqueues decompression into `out` on the current stream (asynchronous); status is i32[1].
+
+    `out` must have the stream's dtype: the library takes its capacity in values of that dtype.
+    Without `dtype_bytes` the header is read to check it (a 64-byte copy that synchronises);
+    a caller that already knows the stream's element size (from ``stream_info``) passes it, and
+    with the block length as well only the matching decoder is launched
+    (``pcomp_decompress_typed``)."""
+    _check_decode_args(stream, out, status)
     w = stream_info(stream)[1] if dtype_bytes is None else int(dtype_bytes)
     _require(_DT[out.dtype] == w, "out has the stream's dtype (%d bytes per value)" % w)
+    if block_len is not None:
+        rc = lib().pcomp_decompress_typed(ctypes.c_void_p(stream.data_ptr()), stream.numel(), w, int(block_len),
+                                          ctypes.c_void_p(out.data_ptr()), out.numel(),
+                                          ctypes.c_void_p(status.data_ptr()), _stream_handle())
+        _check(rc, "pcomp_decompress_typed")
+        return
     rc = lib().pcomp_decompress(ctypes.c_void_p(stream.data_ptr()), stream.numel(), ctypes.c_void_p(out.data_ptr()),
                                 out.numel(), ctypes.c_void_p(status.data_ptr()), _stream_handle())
     _check(rc, "pcomp_decompress")
@@ -193,11 +214,59 @@ def decompress(stream: torch.Tensor) -> torch.Tensor:
     n, w, L, tot = stream_info(stream)
     out = torch.empty(max(n, 1), dtype=_TORCH[w], device=stream.device)
     status = torch.zeros(1, dtype=torch.int32, device=stream.device)
-    decompress_into(stream, out, status, dtype_bytes=w)
+    decompress_into(stream, out, status, dtype_bytes=w, block_len=L)
     st = int(status.item())
     if st != OK:
         raise PcompError(st, "pcomp_decompress (device status)")
     return out[:n]
+
+
+def compress_transposed(x: torch.Tensor, block_len: int, variant: int = 0) -> torch.Tensor:
+    """Time-major blocking of matrices x [n_mat, rows, cols] (e.g. camera events [events,
+    pixels, samples]): the stream of their transposes, read without a transposed copy
+    (``pcomp_compress_transposed``)."""
+    _require(_is_values(x) and x.dim() == 3 and x.shape[1] > 0 and x.shape[2] > 0,
+             "x is a contiguous [n_mat, rows, cols] u8/u16/u32 CUDA tensor")
+    n_mat, rows, cols = x.shape
+    n, w = x.numel(), _DT[x.dtype]
+    cap = bound(n, w, block_len, variant)
+    if cap == 0:
+        raise PcompError(EINVAL, "pcomp_bound")
+    out = torch.empty(cap, dtype=torch.uint8, device=x.device)
+    ws = torch.empty(max(8, workspace_size(n, w, block_len, variant)), dtype=torch.uint8, device=x.device)
+    size = torch.zeros(1, dtype=torch.int64, device=x.device)
+    rc = lib().pcomp_compress_transposed(ctypes.c_void_p(x.data_ptr()), n_mat, rows, cols, w, block_len, variant,
+                                         ctypes.c_void_p(out.data_ptr()), cap, ctypes.c_void_p(size.data_ptr()),
+                                         ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_handle())
+    _check(rc, "pcomp_compress_transposed")
+    err = int(ws[:4].view(torch.int32).item())
+    if err:
+        raise PcompError(EHIP, "pcomp_compress_transposed (device error word %d)" % err)
+    return out[:int(size.item())]
+
+
+def integrate(traces: torch.Tensor) -> torch.Tensor:
+    """Integrated signal (``pcomp_integrate``): the u32 sum of every trace of traces [..., samples]."""
+    _require(_is_values(traces) and traces.dim() >= 1 and traces.shape[-1] > 0,
+             "traces is a contiguous [..., samples] u8/u16/u32 CUDA tensor")
+    samples = traces.shape[-1]
+    n = traces.numel() // samples
+    out = torch.empty(traces.shape[:-1], dtype=torch.uint32, device=traces.device)
+    rc = lib().pcomp_integrate(ctypes.c_void_p(traces.data_ptr()), _DT[traces.dtype], n, samples,
+                               ctypes.c_void_p(out.data_ptr()), _stream_handle())
+    _check(rc, "pcomp_integrate")
+    return out
+
+
+def decompress_transposed_into(stream: torch.Tensor, out: torch.Tensor, status: torch.Tensor, block_len: int) -> None:
+    """Enqueues decompression of a time-major stream back into matrices out [n_mat, rows, cols]."""
+    _check_decode_args(stream, out, status)
+    _require(out.dim() == 3, "out is [n_mat, rows, cols]")
+    n_mat, rows, cols = out.shape
+    rc = lib().pcomp_decompress_transposed(ctypes.c_void_p(stream.data_ptr()), stream.numel(), _DT[out.dtype],
+                                           int(block_len), n_mat, rows, cols, ctypes.c_void_p(out.data_ptr()),
+                                           out.numel(), ctypes.c_void_p(status.data_ptr()), _stream_handle())
+    _check(rc, "pcomp_decompress_transposed")
 
 
 def atlas_info(B: int):
@@ -248,11 +317,9 @@ class _Plan:
         self.host = (ctypes.c_uint64 * ((nb + 7) // 8))()
         _check(lib().pcomp_batch_plan(self.segs, self.n_segs, self.L, self.variant, self.host, nb), "pcomp_batch_plan")
         ob, wb, nt = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
-        offs = (ctypes.c_uint64 * max(1, self.n_segs))()
-        _check(lib().pcomp_batch_info(self.host, ctypes.byref(ob), ctypes.byref(wb), ctypes.byref(nt), offs),
+        _check(lib().pcomp_batch_info(self.host, ctypes.byref(ob), ctypes.byref(wb), ctypes.byref(nt)),
                "pcomp_batch_info")
-        self.out_bytes, self.ws_bytes, self.n_tiles = ob.value, wb.value, nt.value
-        self.offsets = [offs[i] for i in range(self.n_segs)]
+        self.out_capacity, self.ws_bytes, self.n_tiles = ob.value, wb.value, nt.value
         raw = bytes(memoryview(self.host).cast("B")[:nb])
         self.device = torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(device)
 
@@ -261,7 +328,9 @@ class Batch:
     """Compression of a list of segments (any mix of u8/u16/u32 CUDA tensors and lengths) by one
     fixed sequence of launches. Buffers are allocated once; ``compress()`` enqueues the launches
     on the current stream and allocates nothing, so it can be captured in a HIP graph
-    (``capture()``). Each segment becomes its own stream, identical to ``compress(segment)``.
+    (``capture()``). Each segment becomes its own stream, identical to ``compress(segment)``;
+    the streams follow one another in ``out`` in the segments' order, ``seg_offsets`` (device)
+    says where each starts and ``total`` (device) how many bytes they take together.
     ``grid`` = 0 runs one workgroup per tile; otherwise the per-tile launches are persistent
     with that many workgroups."""
 
@@ -270,19 +339,17 @@ class Batch:
         self.variant, self.grid = int(variant), int(grid)
         self.block_len = _block_lens(block_len)
         self.plan = _Plan(self.tensors, self.block_len, self.variant, device)
-        self.out = torch.empty(max(8, self.plan.out_bytes), dtype=torch.uint8, device=device)
+        self.out = torch.empty(max(8, self.plan.out_capacity), dtype=torch.uint8, device=device)
         self.ws = torch.empty(max(8, self.plan.ws_bytes), dtype=torch.uint8, device=device)
-        self.sizes = torch.zeros(max(1, self.plan.n_segs), dtype=torch.int64, device=device)
+        self.seg_offsets = torch.zeros(max(1, self.plan.n_segs), dtype=torch.int64, device=device)
+        self.total = torch.zeros(1, dtype=torch.int64, device=device)
         self.graph = None
-
-    @property
-    def offsets(self):
-        return self.plan.offsets
 
     def compress(self) -> None:
         rc = lib().pcomp_compress_batch(self.plan.host, ctypes.c_void_p(self.plan.device.data_ptr()),
                                         ctypes.c_void_p(self.out.data_ptr()), self.out.numel(),
-                                        ctypes.c_void_p(self.sizes.data_ptr()), ctypes.c_void_p(self.ws.data_ptr()),
+                                        ctypes.c_void_p(self.seg_offsets.data_ptr()),
+                                        ctypes.c_void_p(self.total.data_ptr()), ctypes.c_void_p(self.ws.data_ptr()),
                                         self.ws.numel(), self.grid, _stream_handle())
         _check(rc, "pcomp_compress_batch")
 
@@ -301,19 +368,29 @@ class Batch:
         return int(self.ws[:4].view(torch.int32).item())
 
     def total_bytes(self) -> int:
-        return int(self.sizes[:self.plan.n_segs].sum().item())
+        return int(self.total.item())
 
-    def streams(self):
-        """Views of every segment's stream (synchronises)."""
+    def offsets(self):
+        """Where every segment's stream starts in ``out`` (synchronises)."""
+        return self.seg_offsets[:self.plan.n_segs].tolist()
+
+    def file(self) -> torch.Tensor:
+        """The whole compressed batch: the first ``total`` bytes of ``out`` (synchronises)."""
         err = self.error_flag()
         if err:
             raise PcompError(EHIP, "pcomp_compress_batch (device error word %d)" % err)
-        sz = self.sizes[:self.plan.n_segs].tolist()
-        return [self.out[o:o + s] for o, s in zip(self.plan.offsets, sz)]
+        return self.out[:self.total_bytes()]
+
+    def streams(self):
+        """Views of every segment's stream (synchronises)."""
+        f = self.file()
+        offs = self.offsets() + [f.numel()]
+        return [f[offs[i]:offs[i + 1]] for i in range(self.plan.n_segs)]
 
 
 class BatchDecoder:
-    """Decompression of a Batch's buffer into destination tensors shaped like its segments."""
+    """Decompression of a compressed batch (a Batch's ``out``, or a copy of its first ``total``
+    bytes, with its ``seg_offsets``) into destination tensors shaped like its segments."""
 
     def __init__(self, batch: Batch, outs, grid=0):
         _require(len(outs) == len(batch.tensors), "one destination per segment")
@@ -321,14 +398,18 @@ class BatchDecoder:
             _require(o.numel() == t.numel() and o.dtype == t.dtype, "destinations are shaped like the segments")
         self.batch, self.outs, self.grid = batch, list(outs), int(grid)
         self.plan = _Plan(self.outs, batch.block_len, batch.variant, batch.out.device)
-        _require(self.plan.offsets == batch.plan.offsets, "destination plan matches the batch's")
         self.status = torch.zeros(1, dtype=torch.int32, device=batch.out.device)
 
-    def __call__(self, buf: torch.Tensor = None) -> None:
+    def __call__(self, buf: torch.Tensor = None, seg_offsets: torch.Tensor = None) -> None:
         buf = self.batch.out if buf is None else buf
+        offs = self.batch.seg_offsets if seg_offsets is None else seg_offsets
         _require(buf.is_cuda and buf.dtype == torch.uint8 and buf.is_contiguous(), "buf is a contiguous u8 CUDA tensor")
+        _require(offs.is_cuda and offs.dtype == torch.int64 and offs.is_contiguous() and
+                 offs.numel() >= self.plan.n_segs and offs.device == buf.device,
+                 "seg_offsets holds one i64 per segment, on the device of buf")
         rc = lib().pcomp_decompress_batch(self.plan.host, ctypes.c_void_p(self.plan.device.data_ptr()),
                                           ctypes.c_void_p(buf.data_ptr()), buf.numel(),
+                                          ctypes.c_void_p(offs.data_ptr()),
                                           ctypes.c_void_p(self.status.data_ptr()), self.grid, _stream_handle())
         _check(rc, "pcomp_decompress_batch")
 

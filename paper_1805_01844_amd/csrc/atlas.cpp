@@ -43,8 +43,17 @@ Magic magic_host(uint64_t d) {
     return mg;
 }
 
+uint32_t k_host(uint64_t B);
+
 Chunk chunk_host(uint64_t B) {
     Chunk c{};
+    c.rB = 1.0 / (double)B;  // IEEE division: correctly rounded
+    const uint32_t k = k_host(B);
+    c.h2 = k / 2 > 1 ? k / 2 : 1;
+    uint64_t P2 = 1;
+    for (uint32_t i = 0; i < c.h2; i++) P2 *= B;  // at most 2^32
+    c.P2 = (double)P2;
+    c.rP2 = 1.0 / (double)P2;
     if (B >= (1ull << 24)) return c;  // h = 0
     uint64_t P = 1;
     uint32_t h = 0;
@@ -54,8 +63,6 @@ Chunk chunk_host(uint64_t B) {
     }
     c.h = h;
     c.P = (uint32_t)P;
-    c.mP = magic_host(P);
-    c.rB = 1.0 / (double)B;  // IEEE division: correctly rounded
     return c;
 }
 
@@ -78,7 +85,6 @@ void build_base(uint64_t B, BaseDesc &D, std::vector<AtlasEntry> &ent) {
     bk *= B;
     D.Qk = (uint64_t)(kTwo64 / bk);
     D.mBp[1] = magic_host(bk < kTwo64 ? (uint64_t)bk : 1);
-    D.mB = magic_host(B);
     D.ch = chunk_host(B);
     D.off = (uint32_t)ent.size();
     std::unordered_map<uint64_t, uint32_t> seen;
@@ -160,17 +166,22 @@ int tables_for_current_device(DevTables *out) {
     DeviceTables &D = g_dev[dev];
     if (!D.ready) {
         build_host_tables();
-        void *pd = nullptr, *pe = nullptr, *pk = nullptr;
+        void *pd = nullptr, *pe = nullptr, *pk = nullptr, *pt = nullptr;
         size_t bd = sizeof(BaseDesc) * g_desc->size(), be = sizeof(AtlasEntry) * g_ent->size();
         if (hipMalloc(&pd, bd) != hipSuccess) return PCOMP_EHIP;
         if (hipMalloc(&pe, be) != hipSuccess) return PCOMP_EHIP;
         if (hipMalloc(&pk, sizeof(g_kmax)) != hipSuccess) return PCOMP_EHIP;
+        std::vector<uint8_t> ktab(kAtlasDirect + 1, 0);
+        for (uint32_t B = 2; B <= kAtlasDirect; B++) ktab[B] = (uint8_t)(*g_desc)[B].k;
+        if (hipMalloc(&pt, ktab.size()) != hipSuccess) return PCOMP_EHIP;
+        if (hipMemcpy(pt, ktab.data(), ktab.size(), hipMemcpyHostToDevice) != hipSuccess) return PCOMP_EHIP;
         if (hipMemcpy(pd, g_desc->data(), bd, hipMemcpyHostToDevice) != hipSuccess) return PCOMP_EHIP;
         if (hipMemcpy(pe, g_ent->data(), be, hipMemcpyHostToDevice) != hipSuccess) return PCOMP_EHIP;
         if (hipMemcpy(pk, g_kmax, sizeof(g_kmax), hipMemcpyHostToDevice) != hipSuccess) return PCOMP_EHIP;
         D.t.desc = (const BaseDesc *)pd;
         D.t.ent = (const AtlasEntry *)pe;
         D.t.kmax = (const uint64_t *)pk;
+        D.t.ktab = (const uint8_t *)pt;
         D.ready = true;
     }
     *out = D.t;

@@ -1,25 +1,28 @@
 // compress.hip -- compression kernels (gfx950).
 //
 // A call compresses a table of segments (one for a single stream, thousands for a batch),
-// each into its own stream. Tiles are numbered across the whole table; segments of one
-// element width form a group whose tiles one launch of each width-specialised kernel
-// covers. Four launches, with no communication between workgroups inside any of them:
-//   1. prep_kernel: clears the error word, fills the size tables of every group and writes
-//      the header of every empty segment.
+// each into its own stream, the streams one after another in the caller's order. Tiles are
+// numbered across the whole table; segments of one element width form a group whose tiles
+// one launch of each width-specialised kernel covers. Five steps, with no communication
+// between workgroups inside any launch:
+//   1. prep_kernel: clears the error word and fills the size tables of every group.
 //   2. stats_kernel<W>, per tile of tile_blocks blocks (at most 16 KiB of input): stage the
 //      tile in LDS with 128-bit loads; per block (a group of G = 256 / tile_blocks lanes) min
 //      and max by wavefront shuffles, B = max - min + 1 (Sec. 3, Sec. 3.1), and when
 //      threshold classes are possible the counts of digits at or above 2^(beta - t); size the
 //      candidate classes (basic Sec. 3.1 Eq. (1)-(2), advanced Sec. 3.2 series,
-//      threshold/excess split), keep the smallest (ties to the lowest id), write the block
-//      arrays of the stream and the tile's word total.
+//      threshold/excess split), keep the smallest (ties to the lowest id), write the block's
+//      record (min, B - 1, class, words, n_e) to the workspace and the tile's word total.
 //   3. scan_sums_kernel + scan_prefix_kernel: exclusive prefix sum of all tile totals.
-//   4. pack_kernel<W>, per tile: the tile's payload offset in its stream is its prefix minus
-//      that of the segment's first tile; stage the tile again, read its block arrays, compact
-//      the excess lists of threshold blocks, and pack: the lanes of a block's group take its
-//      words in turn, each word a 64-bit Horner multiply-add over its digits, the first digit
-//      at the highest power. The tile writes its index entry; the segment's last tile writes
-//      the stream header and size.
+//   4. place_kernel (one workgroup): every stream's size (its fixed part plus its payload
+//      words), their exclusive prefix in the caller's order = where each stream starts, the
+//      total, and the headers of streams without values.
+//   5. pack_kernel<W>, per tile: the tile's payload offset in its stream is its prefix minus
+//      that of the segment's first tile; stage the tile again, read its block records, write
+//      its part of the stream's block arrays, compact the excess lists of threshold blocks,
+//      and pack: the lanes of a block's group take its words in turn, each word a 64-bit
+//      Horner multiply-add over its digits, the first digit at the highest power. The tile
+//      writes its index entry; the segment's last tile writes the stream header.
 // The stats and pack launches are persistent when the caller gives a grid smaller than the
 // tile count: each workgroup then walks the tiles with a stride of the grid.
 #include <atomic>
@@ -37,14 +40,20 @@ static_assert(kFeatWords * 4 * kMaxTileBlocks <= kTileBytes, "features must fit 
 
 struct CompressArgs {
     const SegDesc *segs;        // device table of the batch, or nullptr: the one segment is `one`
-    const uint32_t *tile_seg;   // segment of every global tile (batch)
+    const uint32_t *tile_seg;   // plan index of the segment of every global tile (batch)
+    const uint32_t *user_seg;   // plan index of every segment, in the caller's order (batch)
     SegDesc one;
-    uint64_t tile_lo, tile_hi;  // their global tiles
-    uint8_t *out;               // base of every segment's stream
-    uint64_t *sizes;            // stream bytes per segment, by the caller's index
+    uint64_t tile_lo, tile_hi;  // global tiles of this launch's width group
+    uint8_t *out;               // every segment's stream, one after another in the caller's order
+    uint64_t *seg_off;          // [n_segs] byte offset of every segment's stream, plan order (place -> pack)
+    uint64_t *seg_offsets;      // the same offsets in the caller's order, for the caller (or nullptr)
+    uint64_t *total;            // bytes of all streams (device u64, for the caller)
     uint32_t *tile_words;       // [n_tiles] words of every tile (stats -> scan)
-    uint64_t *prefix;           // [n_tiles] exclusive prefix of tile_words (scan -> pack)
+    uint64_t *prefix;           // [n_tiles + 1] exclusive prefix of tile_words, then their sum (scan -> place, pack)
+    uint8_t *rec;               // block records of this launch's width group (stats -> pack)
+    uint64_t rec_n;             // record slots of the group: its tiles x tile_blocks
     uint64_t n_tiles;
+    uint32_t n_segs;
     uint32_t *err;
     const SizeCtx *ctx;         // size tables of this group's block length
     int variant;
@@ -52,14 +61,35 @@ struct CompressArgs {
 };
 
 // Segment holding global tile gt (the plan maps every tile to its segment), in scalar
-// registers.
-__device__ __forceinline__ SegDesc seg_of(const CompressArgs &a, uint64_t gt) {
-    if (a.segs) return uniform_seg(a.segs[uni32(a.tile_seg[gt])]);
+// registers, and its plan index.
+__device__ __forceinline__ SegDesc seg_of(const CompressArgs &a, uint64_t gt, uint32_t &j) {
+    if (a.segs) {
+        j = uni32(a.tile_seg[gt]);
+        return uniform_seg(a.segs[j]);
+    }
+    j = 0;
     return a.one;
 }
 
-__device__ void write_header(uint8_t *s, const Layout &lo, int variant, uint64_t payload_words,
-                             uint64_t *size_slot) {
+// Block records in the workspace, structure of arrays per width group: min and B - 1 at the
+// element width, then one u32 of class (bits 0-3), words (bits 4-15) and n_e (bits 16-31).
+// Block b of global tile gt has slot (gt - tile_lo) * tile_blocks + b.
+__host__ __device__ inline uint64_t rec_bytes(uint64_t slots, uint32_t w) {
+    return 2 * ((w * slots + 7) & ~7ull) + ((4 * slots + 7) & ~7ull);
+}
+template <int W>
+struct Recs {
+    uint8_t *min, *rng;
+    uint32_t *meta;
+    __device__ Recs(uint8_t *base, uint64_t slots) {
+        const uint64_t a = (W * slots + 7) & ~7ull;
+        min = base;
+        rng = base + a;
+        meta = (uint32_t *)(base + 2 * a);
+    }
+};
+
+__device__ void write_header(uint8_t *s, const Layout &lo, int variant, uint64_t payload_words) {
     const uint64_t total = lo.off_payload + 8 * payload_words;
     const uint32_t sel = variant == PCOMP_SELECT_EXHAUSTIVE ? 1 : variant == PCOMP_SELECT_LEARNED ? 2 : 0;
     const uint32_t fixed = (lo.flags & kFlagClass) ? 0 : (uint32_t)variant;
@@ -76,7 +106,6 @@ __device__ void write_header(uint8_t *s, const Layout &lo, int variant, uint64_t
     const uint64_t end_arrays =
         lo.off_ne + ((lo.flags & kFlagNe) ? lo.n_blocks * ((lo.flags & kFlagNe16) ? 2 : 1) : 0);
     for (uint64_t b = end_arrays; b < lo.off_payload; b++) s[b] = 0;
-    *size_slot = total;
 }
 
 // Advanced part whose base is outside the tables: the state of word i depends on every
@@ -223,6 +252,22 @@ __device__ __forceinline__ const typename Elem<W>::T *stage_tile(const uint8_t *
     return (const V *)(s_bytes + head);
 }
 
+// Stages a tile of a time-major segment: value v0 + j of the stream is gathered from the
+// element of the caller's matrices it stands for (one load per value).
+template <int W>
+__device__ __forceinline__ const typename Elem<W>::T *stage_tile_tm(const SegDesc &sd, uint64_t v0, uint32_t nvt,
+                                                                     uint4 *s_raw) {
+    typedef typename Elem<W>::T V;
+    V *dst = (V *)s_raw;
+    const __attribute__((address_space(1))) V *src = (const __attribute__((address_space(1))) V *)sd.data;
+    TmCursor cur(v0 + threadIdx.x, sd.rows, sd.cols);
+    for (uint32_t j = threadIdx.x; j < nvt; j += kThreads) {
+        dst[j] = src[cur.index()];
+        cur.step();
+    }
+    return dst;
+}
+
 // Staging of a tile's input with every load in flight at once: the 16-byte chunks that lie
 // inside the segment go through buffer loads into registers (a chunk that is not loaded gets an
 // offset past the buffer's range, which reads zeros without touching memory, so the loads are
@@ -328,17 +373,19 @@ __global__ __launch_bounds__(kThreads) void stats_kernel(CompressArgs a) {
     if (kLearned)
         for (uint32_t i = tid; i < (uint32_t)kMlpParams; i += kThreads) s_model[i] = c_model[i];
     for (uint64_t gt = a.tile_lo + blockIdx.x; gt < a.tile_hi; gt = kPersist ? gt + gridDim.x : a.tile_hi) {
-        const SegDesc sd = seg_of(a, gt);
+        uint32_t sj;
+        const SegDesc sd = seg_of(a, gt, sj);
         const Layout &lo = sd.lo;
         const uint32_t L = lo.L, tb = lo.tile_blocks;
-        uint8_t *so = a.out + sd.out_off;
         const uint64_t b0 = (gt - sd.tile0) * tb;
         const uint32_t nbt = (uint32_t)min((uint64_t)tb, lo.n_blocks - b0);
         const uint64_t v0 = b0 * L;
         const uint32_t nvt = (uint32_t)min((uint64_t)nbt * L, lo.n - v0);
         // one workgroup per tile: all of its loads at once (persistent grids keep fewer registers)
         const V *s_val;
-        if (kPersist) {
+        if (sd.rows) {
+            s_val = stage_tile_tm<W>(sd, v0, nvt, s_raw);
+        } else if (kPersist) {
             s_val = stage_tile<W>(sd.data, v0, nvt, s_raw);
         } else {
             const TileRef tr = tile_ref<W>(sd, v0, nvt);
@@ -521,12 +568,11 @@ __global__ __launch_bounds__(kThreads) void stats_kernel(CompressArgs a) {
         for (int tt = 1; tt < 8; tt++) ne = (tcls == tt) ? ne_t[tt] : ne;
         if (live && g == 0) {
             s_nw[blk] = nw;
-            const uint64_t gb = b0 + blk;
-            put_le(so + lo.off_min + gb * W, vmin, W);
-            put_le(so + lo.off_range + gb * W, B - 1, W);
-            if (lo.flags & kFlagClass) so[lo.off_class + gb] = (uint8_t)cls;
-            if (lo.flags & kFlagNe)
-                put_le(so + lo.off_ne + gb * ((lo.flags & kFlagNe16) ? 2 : 1), ne, (lo.flags & kFlagNe16) ? 2 : 1);
+            const uint64_t r = (gt - a.tile_lo) * tb + blk;
+            const Recs<W> rc(a.rec, a.rec_n);
+            ((V *)rc.min)[r] = (V)vmin;
+            ((V *)rc.rng)[r] = (V)(B - 1);
+            rc.meta[r] = (uint32_t)cls | (nw << 4) | (ne << 16);
         }
         __syncthreads();
         uint32_t total;
@@ -580,7 +626,43 @@ __global__ __launch_bounds__(kThreads) void scan_prefix_kernel(CompressArgs a, c
     for (uint32_t m = 0; m < kScanPer; m++) {
         if (t0 + m < nt) a.prefix[t0 + m] = run;
         run += v[m];
+        if (t0 + m + 1 == nt) a.prefix[nt] = run;  // the sum of every tile
     }
+}
+
+// ---- launch 4: placement of the streams --------------------------------------------------
+// One workgroup. Stream sizes (fixed part + 8 x payload words, from the tile prefix), their
+// exclusive prefix in the caller's order, the total, and the header of every stream without
+// values (no tile of it runs in the packing launch).
+__global__ __launch_bounds__(kThreads) void place_kernel(CompressArgs a) {
+    __shared__ uint64_t s_red64[kThreads / 64];
+    const uint32_t n = a.n_segs;
+    const uint32_t per = (n + kThreads - 1) / kThreads;
+    const uint32_t u0 = min(n, threadIdx.x * per), u1 = min(n, u0 + per);
+    auto seg = [&](uint32_t u, uint32_t &j) -> SegDesc {
+        j = a.segs ? a.user_seg[u] : 0;
+        return a.segs ? a.segs[j] : a.one;
+    };
+    auto size_of = [&](const SegDesc &sd) -> uint64_t {
+        const uint64_t pw = sd.lo.n_tiles ? a.prefix[sd.tile0 + sd.lo.n_tiles] - a.prefix[sd.tile0] : 0;
+        return sd.lo.off_payload + 8 * pw;
+    };
+    uint64_t sum = 0;
+    for (uint32_t u = u0; u < u1; u++) {
+        uint32_t j;
+        sum += size_of(seg(u, j));
+    }
+    uint64_t tot;
+    uint64_t run = wg_excl_scan64(sum, s_red64, &tot);
+    for (uint32_t u = u0; u < u1; u++) {
+        uint32_t j;
+        const SegDesc sd = seg(u, j);
+        a.seg_off[j] = run;
+        if (a.seg_offsets) a.seg_offsets[u] = run;
+        if (sd.lo.n_tiles == 0) write_header(a.out + run, sd.lo, a.variant, 0);
+        run += size_of(sd);
+    }
+    if (threadIdx.x == 0) *a.total = tot;
 }
 
 // ---- launch 4: packing ----------------------------------------------------------------
@@ -606,10 +688,11 @@ __global__ __launch_bounds__(kThreads) void pack_kernel(CompressArgs a) {
     copy_size_ctx(a.ctx, s_C);
     __syncthreads();  // the size tables are read before the first barrier of a tile
     for (uint64_t gt = a.tile_lo + blockIdx.x; gt < a.tile_hi; gt = kPersist ? gt + gridDim.x : a.tile_hi) {
-        const SegDesc sd = seg_of(a, gt);
+        uint32_t sj;
+        const SegDesc sd = seg_of(a, gt, sj);
         const Layout &lo = sd.lo;
         const uint32_t L = lo.L, tb = lo.tile_blocks;
-        uint8_t *so = a.out + sd.out_off;
+        uint8_t *so = a.out + uni64(a.seg_off[sj]);
         const uint64_t tile = gt - sd.tile0;
         const uint64_t b0 = tile * tb;
         const uint32_t nbt = (uint32_t)min((uint64_t)tb, lo.n_blocks - b0);
@@ -622,40 +705,43 @@ __global__ __launch_bounds__(kThreads) void pack_kernel(CompressArgs a) {
         const TileRef tr = tile_ref<W>(sd, v0, nvt);
         Staged stg;
         const V *s_val = nullptr;
-        if (kPersist)
+        const bool tm = sd.rows != 0;
+        if (tm)
+            s_val = stage_tile_tm<W>(sd, v0, nvt, s_raw);
+        else if (kPersist)
             s_val = stage_tile<W>(sd.data, v0, nvt, s_raw);
         else
             tile_fetch(tr, stg);
-        // the tile's block arrays, as the statistics launch wrote them, and each block's words.
-        // One scan of packed fields gives each block its word offset, its place among the
-        // tile's excess values and its lane group (basic blocks first, then advanced ones, so
-        // that wavefronts mostly run one family's code).
+        // the tile's block records, as the statistics launch wrote them (class, words and n_e
+        // included), go to the stream's block arrays. One scan of packed fields gives each block
+        // its word offset, its place among the tile's excess values and its lane group (basic
+        // blocks first, then advanced ones, so that wavefronts mostly run one family's code).
         uint64_t key = 0;
         if (tid < nbt) {
             const uint64_t gb = b0 + tid;
-            const uint32_t mn = (uint32_t)get_le(so + lo.off_min + gb * W, W);
-            const uint32_t rg = (uint32_t)get_le(so + lo.off_range + gb * W, W);
-            const int c = (lo.flags & kFlagClass) ? so[lo.off_class + gb] : variant;
-            const uint32_t ne = (lo.flags & kFlagNe) ? (uint32_t)get_le(so + lo.off_ne + gb * ((lo.flags & kFlagNe16) ? 2 : 1),
-                                                                        (lo.flags & kFlagNe16) ? 2 : 1)
-                                                     : 0u;
+            const uint64_t r = (gt - a.tile_lo) * tb + tid;
+            const Recs<W> rc(a.rec, a.rec_n);
+            const uint32_t mn = ((const V *)rc.min)[r];
+            const uint32_t rg = ((const V *)rc.rng)[r];
+            const uint32_t meta = rc.meta[r];
+            const int c = (int)(meta & 15);
+            const uint32_t nw = (meta >> 4) & 0xFFF, ne = meta >> 16;
             s_min[tid] = (V)mn;
             s_rng[tid] = (V)rg;
             s_cls[tid] = (uint8_t)c;
             s_ne[tid] = (uint16_t)ne;
-            const uint32_t Lb = (uint32_t)min((uint64_t)L, lo.n - gb * L);
-            const uint64_t B = (uint64_t)rg + 1;
-            uint32_t nwm;
-            uint32_t nw = class_words<(W == 4)>(T, s_C, L, c, Lb, B, bitlen64(B - 1), ne, nwm);
-            const uint32_t per = 8 / W, cap = (Lb + per - 1) / per;
-            nw = nw < cap ? nw : cap;
+            put_le(so + lo.off_min + gb * W, mn, W);
+            put_le(so + lo.off_range + gb * W, rg, W);
+            if (lo.flags & kFlagClass) so[lo.off_class + gb] = (uint8_t)c;
+            if (lo.flags & kFlagNe)
+                put_le(so + lo.off_ne + gb * ((lo.flags & kFlagNe16) ? 2 : 1), ne, (lo.flags & kFlagNe16) ? 2 : 1);
             const bool adv = c >> 3;
             // words (18 bits: a tile holds at most 2^14 values), excess values (18), basic
             // blocks (9), advanced blocks (9)
             key = (uint64_t)nw | ((uint64_t)(!fixed0 && (c & 7) ? ne : 0) << 18) | ((uint64_t)(adv ? 0 : 1) << 36) |
                   ((uint64_t)(adv ? 1 : 0) << 45);
         }
-        if (!kPersist) s_val = tile_commit<W>(tr, stg, s_raw);
+        if (!kPersist && !tm) s_val = tile_commit<W>(tr, stg, s_raw);
         uint64_t tot;
         const uint64_t exs = wg_excl_scan64(key, s_red64, &tot);
         const uint32_t total = (uint32_t)(tot & 0x3FFFF), extot = (uint32_t)((tot >> 18) & 0x3FFFF);
@@ -716,7 +802,7 @@ __global__ __launch_bounds__(kThreads) void pack_kernel(CompressArgs a) {
         }
         if (tid == 0) {
             ((uint64_t *)(so + lo.off_index))[tile] = base_off;
-            if (tile + 1 == lo.n_tiles) write_header(so, lo, variant, base_off + total, a.sizes + sd.user);
+            if (tile + 1 == lo.n_tiles) write_header(so, lo, variant, base_off + total);
         }
         if (live && nw) {
             uint64_t *dst = (uint64_t *)(so + lo.off_payload) + base_off + s_off[blk];
@@ -745,18 +831,13 @@ __global__ __launch_bounds__(kThreads) void pack_kernel(CompressArgs a) {
 }
 
 // ---- launch 1: per-call preparation --------------------------------------------------------
-// Clears the error word, fills the size tables of the three width groups (block length L[g])
-// and writes the header of every segment without values (its stream has no tiles).
+// Clears the error word and fills the size tables of the three width groups (block length L[g]).
 __global__ __launch_bounds__(kThreads) void prep_kernel(CompressArgs a, SizeCtx *ctx, uint32_t L0, uint32_t L1,
-                                                         uint32_t L2, uint32_t n_segs, const uint16_t *adv_tab) {
+                                                         uint32_t L2, const uint16_t *adv_tab) {
     const uint32_t Ls[3] = {L0, L1, L2};
     for (int g = 0; g < 3; g++)
         if (Ls[g]) fill_size_ctx(a.T, Ls[g], ctx[g], adv_tab ? adv_tab + (size_t)g * kAdvTab : nullptr);
     if (threadIdx.x == 0) *a.err = 0;
-    for (uint32_t s = threadIdx.x; s < n_segs; s += kThreads) {
-        const SegDesc sd = a.segs ? a.segs[s] : a.one;
-        if (sd.lo.n_tiles == 0) write_header(a.out + sd.out_off, sd.lo, a.variant, 0, a.sizes + sd.user);
-    }
 }
 
 // Advanced word counts of a full block (L digits) for every base B <= 2^16 + 1, per call and
@@ -770,12 +851,35 @@ __global__ __launch_bounds__(kThreads) void adv_table_kernel(DevTables T, uint32
 
 // Workspace: [err u32, 0 u32][3 size tables, kCtxBytes each][3 advanced-count tables of
 // kAdvTab u16, padded to 8 bytes][one u32 word total per tile, padded to 8 bytes][one u64
-// prefix per tile][one u64 sum per run of kScanTiles tiles].
+// prefix per tile, then their sum][one u64 sum per run of kScanTiles tiles][one u64 stream
+// offset per segment][the block records of each width group].
 constexpr uint64_t kAdvTabBytes = 3 * ((2ull * kAdvTab + 7) & ~7ull);
-uint64_t compress_ws_bytes(uint64_t n_tiles) {
-    const uint64_t nt = n_tiles ? n_tiles : 1;
-    return 8 + 3 * kCtxBytes + kAdvTabBytes + 4 * ((nt + 1) & ~1ull) + 8 * nt +
-           8 * ((nt + kScanTiles - 1) / kScanTiles);
+struct WsLayout {
+    uint64_t ctx, adv, tile_words, prefix, sums, seg_off, rec[3], rec_n[3], bytes;
+};
+WsLayout ws_layout(uint64_t n_tiles, uint32_t n_segs, const uint64_t *tile_lo, const uint64_t *tile_hi,
+                   const uint32_t *L) {
+    WsLayout w;
+    const uint64_t nt = n_tiles;
+    w.ctx = 8;
+    w.adv = w.ctx + 3 * kCtxBytes;
+    w.tile_words = w.adv + kAdvTabBytes;
+    w.prefix = w.tile_words + 4 * ((nt + 1) & ~1ull);
+    w.sums = w.prefix + 8 * (nt + 1);
+    w.seg_off = w.sums + 8 * ((nt + kScanTiles - 1) / kScanTiles);
+    uint64_t o = w.seg_off + 8 * (uint64_t)n_segs;
+    for (int g = 0; g < 3; g++) {
+        const uint32_t wb = 1u << g;
+        w.rec_n[g] = L[g] ? (tile_hi[g] - tile_lo[g]) * tile_blocks_of(L[g], wb) : 0;
+        w.rec[g] = o;
+        o += rec_bytes(w.rec_n[g], wb);
+    }
+    w.bytes = o;
+    return w;
+}
+uint64_t compress_ws_bytes(uint64_t n_tiles, uint32_t n_segs, const uint64_t *tile_lo, const uint64_t *tile_hi,
+                           const uint32_t *L) {
+    return ws_layout(n_tiles, n_segs, tile_lo, tile_hi, L).bytes;
 }
 
 // One per-tile launch (stats or pack) of width W; a persistent grid walks the tiles with a
@@ -800,28 +904,37 @@ void launch_tiles(bool stats, bool persist, uint32_t grid, size_t dyn, const Com
     }
 }
 
-// Enqueues the four launches for the segments of one table. `one` is used when segs is
-// nullptr (a single stream). grid = 0 gives the stats and pack launches one workgroup per
-// tile; otherwise they are persistent with that many workgroups.
-int launch_compress_table(const SegDesc *segs, const uint32_t *tile_seg, const SegDesc &one, uint32_t n_segs,
-                          const uint64_t *tile_lo, const uint64_t *tile_hi, const uint32_t *L, uint64_t n_tiles,
-                          int variant, void *d_out, uint64_t *d_sizes, void *ws, uint32_t grid, hipStream_t st) {
+// Enqueues the launches for the segments of one table. `one` is used when segs is nullptr (a
+// single stream). grid = 0 gives the stats and pack launches one workgroup per tile;
+// otherwise they are persistent with that many workgroups. The streams go to d_out one after
+// another in the caller's order; their offsets (caller's order) go to d_seg_offsets when it is
+// not null, and the bytes of all of them to *d_total.
+int launch_compress_table(const SegDesc *segs, const uint32_t *tile_seg, const uint32_t *user_seg, const SegDesc &one,
+                          uint32_t n_segs, const uint64_t *tile_lo, const uint64_t *tile_hi, const uint32_t *L,
+                          uint64_t n_tiles, int variant, void *d_out, uint64_t *d_seg_offsets, uint64_t *d_total,
+                          void *ws, uint32_t grid, hipStream_t st) {
     CompressArgs a;
     if (tables_for_current_device(&a.T) != PCOMP_OK) return PCOMP_EHIP;
     static_assert(sizeof(SizeCtx) <= kCtxBytes, "size tables exceed their workspace slot");
+    const WsLayout wl = ws_layout(n_tiles, n_segs, tile_lo, tile_hi, L);
     uint8_t *wsb = (uint8_t *)ws;
     a.segs = segs;
     a.tile_seg = tile_seg;
+    a.user_seg = user_seg;
     a.one = one;
     a.out = (uint8_t *)d_out;
-    a.sizes = d_sizes;
+    a.seg_offsets = d_seg_offsets;
+    a.total = d_total;
     a.err = (uint32_t *)wsb;
-    SizeCtx *ctx = (SizeCtx *)(wsb + 8);
-    uint16_t *adv_tab = (uint16_t *)(wsb + 8 + 3 * kCtxBytes);
-    const uint64_t nt = n_tiles ? n_tiles : 1;
-    a.tile_words = (uint32_t *)(wsb + 8 + 3 * kCtxBytes + kAdvTabBytes);
-    a.prefix = (uint64_t *)(wsb + 8 + 3 * kCtxBytes + kAdvTabBytes + 4 * ((nt + 1) & ~1ull));
-    uint64_t *sums = a.prefix + nt;
+    SizeCtx *ctx = (SizeCtx *)(wsb + wl.ctx);
+    uint16_t *adv_tab = (uint16_t *)(wsb + wl.adv);
+    a.tile_words = (uint32_t *)(wsb + wl.tile_words);
+    a.prefix = (uint64_t *)(wsb + wl.prefix);
+    uint64_t *sums = (uint64_t *)(wsb + wl.sums);
+    a.seg_off = (uint64_t *)(wsb + wl.seg_off);
+    a.rec = nullptr;
+    a.rec_n = 0;
+    a.n_segs = n_segs;
     a.n_tiles = n_tiles;
     a.variant = variant;
     a.tile_lo = 0;
@@ -833,7 +946,7 @@ int launch_compress_table(const SegDesc *segs, const uint32_t *tile_seg, const S
         if (L[g] && adv_tables)
             adv_table_kernel<<<(kAdvTab + kThreads - 1) / kThreads, kThreads, 0, st>>>(a.T, L[g],
                                                                                       adv_tab + (size_t)g * kAdvTab);
-    prep_kernel<<<1, kThreads, 0, st>>>(a, ctx, L[0], L[1], L[2], n_segs, adv_tables ? adv_tab : nullptr);
+    prep_kernel<<<1, kThreads, 0, st>>>(a, ctx, L[0], L[1], L[2], adv_tables ? adv_tab : nullptr);
     const size_t dyn = 0;
     for (int g = 0; g < 3; g++) {
         const uint64_t ntg = tile_hi[g] - tile_lo[g];
@@ -842,6 +955,8 @@ int launch_compress_table(const SegDesc *segs, const uint32_t *tile_seg, const S
         b.tile_lo = tile_lo[g];
         b.tile_hi = tile_hi[g];
         b.ctx = ctx + g;
+        b.rec = wsb + wl.rec[g];
+        b.rec_n = wl.rec_n[g];
         const bool persist = grid && grid < ntg;
         const uint32_t gg = (uint32_t)(persist ? grid : ntg);
         if (g == 0)
@@ -856,6 +971,7 @@ int launch_compress_table(const SegDesc *segs, const uint32_t *tile_seg, const S
         scan_sums_kernel<<<runs, kThreads, 0, st>>>(a, sums);
         scan_prefix_kernel<<<runs, kThreads, 0, st>>>(a, sums);
     }
+    place_kernel<<<1, kThreads, 0, st>>>(a);
     for (int g = 0; g < 3; g++) {
         const uint64_t ntg = tile_hi[g] - tile_lo[g];
         if (!ntg) continue;
@@ -863,6 +979,8 @@ int launch_compress_table(const SegDesc *segs, const uint32_t *tile_seg, const S
         b.tile_lo = tile_lo[g];
         b.tile_hi = tile_hi[g];
         b.ctx = ctx + g;
+        b.rec = wsb + wl.rec[g];
+        b.rec_n = wl.rec_n[g];
         const bool persist = grid && grid < ntg;
         const uint32_t gg = (uint32_t)(persist ? grid : ntg);
         if (g == 0)
@@ -1002,23 +1120,24 @@ bool model_loaded() {
     return g_model_loaded[dev];
 }
 
-// A single stream: a table of one segment.
+// A single stream: a table of one segment (rows > 0: matrices [rows][cols] read time-major).
 int launch_compress(const void *d_in, const Layout &lo, int variant, void *d_out, uint64_t *d_out_size, void *ws,
-                    hipStream_t st) {
-    SegDesc one;
+                    uint32_t rows, uint32_t cols, hipStream_t st) {
+    SegDesc one = SegDesc();
     one.data = (const uint8_t *)d_in;
-    one.out_off = 0;
     one.lo = lo;
     one.tile0 = 0;
     one.user = 0;
+    one.rows = rows;
+    one.cols = cols;
     const int g = lo.w == 1 ? 0 : lo.w == 2 ? 1 : 2;
     one.group = (uint32_t)g;
     uint32_t L[3] = {0, 0, 0};
     uint64_t tile_lo[3] = {0, 0, 0}, tile_hi[3] = {0, 0, 0};
     tile_hi[g] = lo.n_tiles;
     L[g] = lo.L;
-    return launch_compress_table(nullptr, nullptr, one, 1, tile_lo, tile_hi, L, lo.n_tiles, variant, d_out,
-                                 d_out_size, ws, 0, st);
+    return launch_compress_table(nullptr, nullptr, nullptr, one, 1, tile_lo, tile_hi, L, lo.n_tiles, variant, d_out,
+                                 nullptr, d_out_size, ws, 0, st);
 }
 
 }  // namespace pcomp

@@ -18,16 +18,23 @@ struct DecompressArgs {
     uint8_t *out;
     uint64_t out_cap;
     int32_t *status;
+    uint64_t n_tm;          // time-major output: the stream must hold n_tm values ...
+    uint32_t rows, cols;    // ... of matrices [rows][cols], written back in their own layout (rows = 0: plain)
+    int32_t want_w;         // element width the caller expects (0: any) ...
+    uint32_t want_L;        // ... and block length (with want_w)
+    int32_t report;         // this launch reports an unusable header (one launch of a call does)
     DevTables T;
 };
 
 // A batch: the plan's segment table (values go to each segment's `data`), the map from
-// global tile to segment, and the width group of this launch.
+// global tile to segment, where each segment's stream starts, and the width group of this
+// launch.
 struct BatchDecArgs {
     const SegDesc *segs;
     const uint32_t *tile_seg;
+    const uint64_t *seg_offsets;  // byte offset of every segment's stream, in the caller's order
     uint64_t tile_lo, tile_hi;
-    const uint8_t *in;  // the batch buffer: segment streams at their out_off
+    const uint8_t *in;  // the batch buffer
     uint64_t in_size;
     int32_t *status;
     uint32_t L;         // block length of the group
@@ -203,9 +210,10 @@ __device__ __forceinline__ void unpack_part(const DevTables &T, const PartBase &
 
 // Decodes tile `tile` of the stream at `in` (layout lo, pw payload words, fixed class of a
 // single-class stream) into out. Every thread of the workgroup calls it.
-template <int W, bool kRuns>
+template <int W, bool kRuns, bool kTm = false>
 __device__ __forceinline__ void decode_tile(const DevTables &T, const uint8_t *in, const Layout &lo, uint64_t pw,
-                                            int fixed, uint64_t tile, uint8_t *out, int32_t *status, DecShared &S) {
+                                            int fixed, uint64_t tile, uint8_t *out, int32_t *status, DecShared &S,
+                                            uint32_t rows = 0, uint32_t cols = 0) {
     typedef typename Elem<W>::T V;
     const uint32_t tid = threadIdx.x;
     const uint32_t L = lo.L, tb = lo.tile_blocks;
@@ -413,8 +421,16 @@ __device__ __forceinline__ void decode_tile(const DevTables &T, const uint8_t *i
         }
         __syncthreads();
 
-        // ---- 4. coalesced store of the tile (16-byte stores where the output is aligned)
-        {
+        // ---- 4. coalesced store of the tile (16-byte stores where the output is aligned); a
+        //         time-major stream goes back to the caller's matrices value by value
+        if (kTm) {
+            __attribute__((address_space(1))) V *gv = (__attribute__((address_space(1))) V *)out;
+            TmCursor cur(v0 + tid, rows, cols);
+            for (uint32_t j = tid; j < nvt; j += kThreads) {
+                gv[cur.index()] = s_val[j];
+                cur.step();
+            }
+        } else {
             const uint8_t *sb = (const uint8_t *)S.raw;
             __attribute__((address_space(1))) uint8_t *gdst = (__attribute__((address_space(1))) uint8_t *)(out + v0 * W);
             const uint32_t head = (uint32_t)((16 - ((uintptr_t)gdst & 15)) & 15);
@@ -439,23 +455,26 @@ __device__ __forceinline__ void decode_tile(const DevTables &T, const uint8_t *i
     }
 }
 
-// One kernel per element width and lane-group size (both are only known on the device, from
-// the stream's header): each returns at once unless the header matches it, so only one does
-// the work. Five wavefronts per SIMD (at most 96 vector registers) fit for u8 and u16, and five
-// workgroups per CU fit the LDS (under 32 KiB each, with the 8 KiB excess buffer).
-template <int W, bool kRuns>
+// One kernel per element width and lane-group size (both are known on the device, from the
+// stream's header; a caller that knows them launches only the matching kernel): each returns
+// at once unless the header matches it, so only one does the work. Five wavefronts per SIMD (at
+// most 96 vector registers) fit for u8 and u16, and five workgroups per CU fit the LDS (under
+// 32 KiB each, with the 8 KiB excess buffer).
+template <int W, bool kRuns, bool kTm = false>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(W == 4 ? 4 : 5))) void decompress_kernel(
     DecompressArgs a) {
     __shared__ DecShared S;
     Layout lo;
     uint64_t pw;
     int fixed;
-    const bool ok = read_layout(a.in, a.in_size, lo, pw, fixed);
-    if (W == 1 && !kRuns && !ok) {  // reported once, by one kernel
-        if (blockIdx.x == 0 && threadIdx.x == 0) set_status(a.status, PCOMP_ECORRUPT);
+    const bool ok = read_layout(a.in, a.in_size, lo, pw, fixed) &&
+                    (a.want_w == 0 || ((int32_t)lo.w == a.want_w && lo.L == a.want_L)) &&
+                    (a.rows == 0 || lo.n == a.n_tm);
+    if (!ok) {  // reported once, by one launch
+        if (a.report && blockIdx.x == 0 && threadIdx.x == 0) set_status(a.status, PCOMP_ECORRUPT);
         return;
     }
-    if (!ok || lo.w != W || (kThreads / lo.tile_blocks >= kRunLanes) != kRuns) return;
+    if (lo.w != W || (kThreads / lo.tile_blocks >= kRunLanes) != kRuns) return;
     if ((uint64_t)lo.L * lo.w > kTileBytes) {
         if (blockIdx.x == 0 && threadIdx.x == 0) set_status(a.status, PCOMP_EINVAL);
         return;
@@ -467,7 +486,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(W == 4
     fill_size_ctx(a.T, lo.L, S.C);
     __syncthreads();
     for (uint64_t tile = blockIdx.x; tile < lo.n_tiles; tile += gridDim.x)
-        decode_tile<W, kRuns>(a.T, a.in, lo, pw, fixed, tile, a.out, a.status, S);
+        decode_tile<W, kRuns, kTm>(a.T, a.in, lo, pw, fixed, tile, a.out, a.status, S, a.rows, a.cols);
 }
 
 // Batch: the tiles of one width group, each decoded into its segment's destination. A
@@ -480,11 +499,12 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(W == 4
     __syncthreads();
     for (uint64_t gt = a.tile_lo + blockIdx.x; gt < a.tile_hi; gt += gridDim.x) {
         const SegDesc sd = uniform_seg(a.segs[uni32(a.tile_seg[gt])]);
-        const uint8_t *s = a.in + sd.out_off;
+        const uint64_t off = uni64(a.seg_offsets[sd.user]);
+        const uint8_t *s = a.in + off;
         Layout lo;
         uint64_t pw;
         int fixed;
-        const bool ok = sd.out_off < a.in_size && read_layout(s, a.in_size - sd.out_off, lo, pw, fixed) &&
+        const bool ok = off < a.in_size && (off & 7) == 0 && read_layout(s, a.in_size - off, lo, pw, fixed) &&
                         lo.w == W && lo.n == sd.lo.n && lo.L == sd.lo.L && lo.flags == sd.lo.flags;
         if (!ok) {
             if (threadIdx.x == 0) set_status(a.status, PCOMP_ECORRUPT);
@@ -496,8 +516,12 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(W == 4
 
 __global__ void set_i32_kernel(int32_t *p, int32_t v) { *p = v; }
 
+// want_w = 0: the element width and block length are read on the device, so all six
+// (width, lane-group) kernels are launched and five return at once; otherwise only the kernel
+// for (want_w, want_L) runs, and it reports a header of another width as corrupt. rows > 0: a
+// time-major stream of n_tm values in matrices [rows][cols], written back in their layout.
 int launch_decompress(const void *d_in, size_t in_size, void *d_out, size_t out_capacity, int32_t *d_status,
-                      hipStream_t st) {
+                      int want_w, uint32_t want_L, uint64_t n_tm, uint32_t rows, uint32_t cols, hipStream_t st) {
     DecompressArgs a;
     if (tables_for_current_device(&a.T) != PCOMP_OK) return PCOMP_EHIP;
     set_i32_kernel<<<1, 1, 0, st>>>(d_status, PCOMP_OK);
@@ -506,27 +530,67 @@ int launch_decompress(const void *d_in, size_t in_size, void *d_out, size_t out_
     a.out = (uint8_t *)d_out;
     a.out_cap = out_capacity;
     a.status = d_status;
+    a.n_tm = n_tm;
+    a.rows = rows;
+    a.cols = cols;
+    a.want_w = want_w;
+    a.want_L = want_L;
     // persistent grid: enough workgroups to fill every CU several times over
     const uint64_t max_tiles = in_size > kHdrBytes ? (in_size - kHdrBytes) / 8 : 1;
     const uint32_t grid = (uint32_t)(max_tiles < 1 ? 1 : (max_tiles < 4096 ? max_tiles : 4096));
-    decompress_kernel<1, false><<<grid, kThreads, 0, st>>>(a);
-    decompress_kernel<1, true><<<grid, kThreads, 0, st>>>(a);
-    decompress_kernel<2, false><<<grid, kThreads, 0, st>>>(a);
-    decompress_kernel<2, true><<<grid, kThreads, 0, st>>>(a);
-    decompress_kernel<4, false><<<grid, kThreads, 0, st>>>(a);
-    decompress_kernel<4, true><<<grid, kThreads, 0, st>>>(a);
+    DecompressArgs first = a, rest = a;
+    first.report = 1;
+    rest.report = 0;
+    if (want_w == 0) {
+        decompress_kernel<1, false><<<grid, kThreads, 0, st>>>(first);
+        decompress_kernel<1, true><<<grid, kThreads, 0, st>>>(rest);
+        decompress_kernel<2, false><<<grid, kThreads, 0, st>>>(rest);
+        decompress_kernel<2, true><<<grid, kThreads, 0, st>>>(rest);
+        decompress_kernel<4, false><<<grid, kThreads, 0, st>>>(rest);
+        decompress_kernel<4, true><<<grid, kThreads, 0, st>>>(rest);
+    } else if (rows) {  // time-major: the kernels with the value-by-value store
+        const bool runs = kThreads / tile_blocks_of(want_L, (uint32_t)want_w) >= kRunLanes;
+        if (want_w == 1 && runs)
+            decompress_kernel<1, true, true><<<grid, kThreads, 0, st>>>(first);
+        else if (want_w == 1)
+            decompress_kernel<1, false, true><<<grid, kThreads, 0, st>>>(first);
+        else if (want_w == 2 && runs)
+            decompress_kernel<2, true, true><<<grid, kThreads, 0, st>>>(first);
+        else if (want_w == 2)
+            decompress_kernel<2, false, true><<<grid, kThreads, 0, st>>>(first);
+        else if (runs)
+            decompress_kernel<4, true, true><<<grid, kThreads, 0, st>>>(first);
+        else
+            decompress_kernel<4, false, true><<<grid, kThreads, 0, st>>>(first);
+    } else {
+        const bool runs = kThreads / tile_blocks_of(want_L, (uint32_t)want_w) >= kRunLanes;
+        if (want_w == 1 && runs)
+            decompress_kernel<1, true><<<grid, kThreads, 0, st>>>(first);
+        else if (want_w == 1)
+            decompress_kernel<1, false><<<grid, kThreads, 0, st>>>(first);
+        else if (want_w == 2 && runs)
+            decompress_kernel<2, true><<<grid, kThreads, 0, st>>>(first);
+        else if (want_w == 2)
+            decompress_kernel<2, false><<<grid, kThreads, 0, st>>>(first);
+        else if (runs)
+            decompress_kernel<4, true><<<grid, kThreads, 0, st>>>(first);
+        else
+            decompress_kernel<4, false><<<grid, kThreads, 0, st>>>(first);
+    }
     return hipGetLastError() == hipSuccess ? PCOMP_OK : PCOMP_EHIP;
 }
 
 // Batch decompression: one persistent launch per width group present. grid = 0 picks 4096
 // workgroups (or one per tile when there are fewer tiles).
 int launch_decompress_batch(const BatchPlanHeader &ph, const SegDesc *d_segs, const uint32_t *d_tile_seg,
-                            const void *d_in, size_t in_size, int32_t *d_status, uint32_t grid, hipStream_t st) {
+                            const void *d_in, size_t in_size, const uint64_t *d_seg_offsets, int32_t *d_status,
+                            uint32_t grid, hipStream_t st) {
     BatchDecArgs a;
     if (tables_for_current_device(&a.T) != PCOMP_OK) return PCOMP_EHIP;
     set_i32_kernel<<<1, 1, 0, st>>>(d_status, PCOMP_OK);
     a.segs = d_segs;
     a.tile_seg = d_tile_seg;
+    a.seg_offsets = d_seg_offsets;
     a.in = (const uint8_t *)d_in;
     a.in_size = in_size;
     a.status = d_status;

@@ -124,7 +124,6 @@ __device__ __forceinline__ uint64_t uni64(uint64_t x) {
 __device__ __forceinline__ SegDesc uniform_seg(const SegDesc &s) {
     SegDesc u;
     u.data = (const uint8_t *)uni64((uint64_t)(uintptr_t)s.data);
-    u.out_off = uni64(s.out_off);
     u.lo.n = uni64(s.lo.n);
     u.lo.n_blocks = uni64(s.lo.n_blocks);
     u.lo.n_tiles = uni64(s.lo.n_tiles);
@@ -141,8 +140,39 @@ __device__ __forceinline__ SegDesc uniform_seg(const SegDesc &s) {
     u.tile0 = uni64(s.tile0);
     u.user = uni32(s.user);
     u.group = uni32(s.group);
+    u.rows = uni32(s.rows);
+    u.cols = uni32(s.cols);
     return u;
 }
+
+// Time-major blocking: where value t of the stream sits in the caller's matrices [rows][cols]
+// (t = (e cols + c) rows + r, element (e, r, c)), and the same walk in steps of kThreads.
+struct TmCursor {
+    uint64_t e;
+    uint32_t r, c, rows, cols, dr, dc;
+    __device__ TmCursor(uint64_t t, uint32_t rows_, uint32_t cols_) : rows(rows_), cols(cols_) {
+        const uint64_t mat = (uint64_t)rows * cols;
+        e = t / mat;
+        const uint64_t rem = t - e * mat;
+        c = (uint32_t)(rem / rows);
+        r = (uint32_t)(rem - (uint64_t)c * rows);
+        dc = kThreads / rows;
+        dr = kThreads - dc * rows;
+    }
+    __device__ __forceinline__ uint64_t index() const { return (e * rows + r) * cols + c; }
+    __device__ __forceinline__ void step() {
+        r += dr;
+        c += dc;
+        if (r >= rows) {
+            r -= rows;
+            c++;
+        }
+        while (c >= cols) {
+            c -= cols;
+            e++;
+        }
+    }
+};
 
 struct MinOp {
     __device__ uint32_t operator()(uint32_t a, uint32_t b) const { return a < b ? a : b; }
@@ -166,11 +196,13 @@ struct SizeCtx {
     uint32_t p1_k[32];
     uint32_t p1_adv[32];
     const uint16_t *advL;  // advanced words of a full block for every base <= 2^16 + 1, or nullptr
+    const uint8_t *ktab;   // k(B) for every base <= 2^16 + 1
 };
 
 __device__ inline void fill_size_ctx(const DevTables &T, uint32_t L, SizeCtx &C, const uint16_t *advL = nullptr) {
     const uint32_t t = threadIdx.x;
     if (t == 200) C.advL = advL;
+    if (t == 201) C.ktab = T.ktab;
     if (t < 65) C.kmax[t] = T.kmax[t];
     if (t >= 96 && t < 128) {
         const uint32_t j = t - 96;
@@ -183,6 +215,7 @@ __device__ inline void fill_size_ctx(const DevTables &T, uint32_t L, SizeCtx &C,
 // k(B) = max{k : B^k <= 2^64} for B >= 2 (Sec. 3.1 Eq. (1), exact reading), from a float
 // estimate corrected against the exact table.
 __device__ __forceinline__ uint32_t k_fast(const SizeCtx &C, uint64_t B) {
+    if (B <= kAtlasDirect) return ((const __attribute__((address_space(1))) uint8_t *)C.ktab)[B];  // global, not flat
     uint32_t k = (uint32_t)(64.0f * __builtin_amdgcn_rcpf(__log2f((float)B)));  // corrected below
     k = k < 1 ? 1 : (k > 63 ? 63 : k);
     const uint64_t cur = C.kmax[k], up = C.kmax[k + 1];  // both bounds fetched together
@@ -328,36 +361,42 @@ __device__ __forceinline__ uint32_t hist_bin(const Hist16 &h, int b) {
 // ---------------------------------------------------------------------------------------
 // Digit arithmetic in 32-bit chunks (see Chunk).
 // ---------------------------------------------------------------------------------------
-// Peels cnt base-B digits off a chunk value xf < 2^32 (held exactly in binary64), lowest
-// first, to put(--j, digit); returns what remains. Each quotient is trunc(fma(x, rB, rB/2)),
-// rB = 1/B rounded to nearest: that is (x + 1/2) / B within a relative 2^-52, an error below
-// 2^-20 / B, while (x + 1/2) / B lies at least 1/(2B) from every integer; so the truncation
-// is floor(x / B) exactly, and fma(-q, B, x) is the exact remainder.
-template <typename Put>
-__device__ __forceinline__ double chunk_digits(double xf, double rB, double hB, double Bf, uint32_t &j, uint32_t cnt,
-                                               Put put) {
-    uint32_t m = cnt;
-    for (; m >= 2; m -= 2) {
-        const double q0 = __builtin_trunc(__builtin_fma(xf, rB, hB));
-        put(--j, (uint32_t)__builtin_fma(-q0, Bf, xf));
-        const double q1 = __builtin_trunc(__builtin_fma(q0, rB, hB));
-        put(--j, (uint32_t)__builtin_fma(-q1, Bf, q0));
-        xf = q1;
-    }
-    if (m) {
-        const double q0 = __builtin_trunc(__builtin_fma(xf, rB, hB));
-        put(--j, (uint32_t)__builtin_fma(-q0, Bf, xf));
-        xf = q0;
-    }
-    return xf;
+// One base-B digit off x < 2^51 (held exactly in binary64): returns floor(x / B) and sets
+// d = x mod B. The quotient is trunc(fma(x, rB, rB/2)) with rB = 1/B rounded to nearest:
+// (x + 1/2) / B lies at least 1/(2B) from every integer (2x + 1 is odd), and the computed value
+// is within a relative 2^-52 of it, an error below (x + 1/2) 2^-52 / B < 1/(2B) for x < 2^51;
+// so the truncation is floor(x / B) exactly, and fma(-q, B, x) is the exact remainder.
+__host__ __device__ __forceinline__ double digit_off(double x, double rB, double hB, double Bf, uint32_t &d) {
+    const double q = __builtin_trunc(__builtin_fma(x, rB, hB));
+    d = (uint32_t)__builtin_fma(-q, Bf, x);
+    return q;
+}
+
+// Splits X < 2^64 at P (2^13 <= P <= 2^32, exact in binary64; rP = 1/P rounded to nearest):
+// hi = floor(X / P) < 2^51 and lo = X mod P, both exact binary64 integers.
+// With X = xh 2^32 + xl: q1 = floor(xh / P) and r1 = xh mod P as in digit_off (xh < 2^32);
+// the rest Y = r1 2^32 + xl < P 2^32 then has Y / P < 2^32, and its binary64 estimate (Y rounded,
+// times rP, plus 2^-18) errs by less than 2^-19.4 before the added 2^-18, so its truncation is
+// floor(Y / P) or one more. lo = Y - q2 P is computed exactly (an integer below 2^34 in
+// magnitude); a negative lo means q2 was one too many.
+__host__ __device__ __forceinline__ void split_word(uint64_t X, double P, double rP, double &hi, double &lo) {
+    const double dh = (double)(uint32_t)(X >> 32), dl = (double)(uint32_t)X;
+    const double q1 = __builtin_trunc(__builtin_fma(dh, rP, 0.5 * rP));
+    const double r1s = __builtin_ldexp(__builtin_fma(-q1, P, dh), 32);  // (xh mod P) 2^32, exact
+    double q2 = __builtin_trunc(__builtin_fma(r1s + dl, rP, 0x1p-18));
+    double r = __builtin_fma(-q2, P, r1s) + dl;
+    const bool over = r < 0.0;
+    r = over ? r + P : r;
+    q2 = over ? q2 - 1.0 : q2;
+    hi = __builtin_ldexp(q1, 32) + q2;  // exact: below 2^51
+    lo = r;
 }
 
 // Resolved constants of one base for packing / unpacking a part of a block.
 struct PartBase {
     uint64_t base;
     uint32_t k;           // digits per basic word
-    Chunk ch;             // 32-bit chunking (h = 0: digit by digit in 64 bits)
-    Magic mB;             // 64-bit division by the base (h = 0 path, and advanced split values)
+    Chunk ch;             // chunking (packing h = 0: digit by digit in 64 bits)
     const BaseDesc *D;    // schedule of the advanced series, nullptr outside the tables
 };
 
@@ -370,12 +409,16 @@ __device__ __forceinline__ PartBase resolve_base(const DevTables &T, const SizeC
         const BaseDesc &D = T.desc[ai >= 0 ? ai : 2];
         pb.k = D.k;
         pb.ch = D.ch;
-        pb.mB = D.mB;
         pb.D = &D;
     } else {
+        // 2^16 + 1 < base <= 2^32: k is 2 or 3, and a word splits after its lowest digit
         pb.k = k_fast(C, base);
         pb.ch.h = 0;
-        pb.mB = magic_dev_outline(base);
+        pb.ch.P = 0;
+        pb.ch.rB = 1.0 / (double)base;
+        pb.ch.h2 = 1;
+        pb.ch.P2 = (double)base;
+        pb.ch.rP2 = pb.ch.rB;
         pb.D = nullptr;
     }
     return pb;
@@ -408,30 +451,49 @@ __device__ __forceinline__ uint64_t horner_digits(const PartBase &pb, uint32_t l
 }
 
 // Peels the lowest cnt base-B digits off X: put(j0 + cnt - 1, lowest digit), ...,
-// put(j0, highest of them); returns what remains above them.
+// put(j0, highest of them); returns what remains above them. cnt >= h2 (every word holds at
+// least k - 1 digits). The word splits once at B^h2 and the two parts give their digits side by
+// side: the lowest h2 from below the split, the other cnt - h2 (and the rest) from above it.
 template <bool Wide, typename Put>
 __device__ __forceinline__ uint64_t peel_digits(const PartBase &pb, uint64_t X, uint32_t j0, uint32_t cnt, Put put) {
-    if (Wide && pb.ch.h == 0) {  // base >= 2^24 (u32 data only)
-        for (int j = (int)cnt - 1; j >= 0; j--) {
-            const uint64_t q = div_magic(X, pb.mB);
-            put(j0 + j, (uint32_t)(X - q * pb.base));
-            X = q;
-        }
-        return X;
+    const double rB = pb.ch.rB, hB = 0.5 * rB, Bf = (double)pb.base;
+    double hi, lo;
+    split_word(X, pb.ch.P2, pb.ch.rP2, hi, lo);
+    const uint32_t nl = pb.ch.h2, nh = cnt - nl;  // nh is nl - 1, nl or nl + 1
+    uint32_t jl = j0 + cnt, jh = j0 + nh;
+    const uint32_t both = nl < nh ? nl : nh;
+    uint32_t m = 0;
+    for (; m + 2 <= both; m += 2) {  // two digits of each part per round
+        uint32_t d0, d1, d2, d3;
+        lo = digit_off(lo, rB, hB, Bf, d0);
+        hi = digit_off(hi, rB, hB, Bf, d1);
+        lo = digit_off(lo, rB, hB, Bf, d2);
+        hi = digit_off(hi, rB, hB, Bf, d3);
+        put(jl - 1, d0);
+        put(jh - 1, d1);
+        put(jl - 2, d2);
+        put(jh - 2, d3);
+        jl -= 2;
+        jh -= 2;
     }
-    const uint32_t h = pb.ch.h;
-    const double rB = pb.ch.rB, hB = 0.5 * rB, Bf = (double)(uint32_t)pb.base;
-    uint32_t j = j0 + cnt;
-    uint32_t rem = cnt;
-    while (rem >= h) {
-        const uint64_t q = div_magic(X, pb.ch.mP);
-        chunk_digits((double)(uint32_t)(X - q * pb.ch.P), rB, hB, Bf, j, h, put);
-        X = q;
-        rem -= h;
+    if (m < both) {
+        uint32_t d0, d1;
+        lo = digit_off(lo, rB, hB, Bf, d0);
+        hi = digit_off(hi, rB, hB, Bf, d1);
+        put(--jl, d0);
+        put(--jh, d1);
     }
-    // fewer than h digits (plus a top digit) remain: X < B^h < 2^32
-    if (rem) X = (uint32_t)chunk_digits((double)(uint32_t)X, rB, hB, Bf, j, rem, put);
-    return X;
+    if (nl > both) {
+        uint32_t d;
+        lo = digit_off(lo, rB, hB, Bf, d);
+        put(--jl, d);
+    }
+    if (nh > both) {
+        uint32_t d;
+        hi = digit_off(hi, rB, hB, Bf, d);
+        put(--jh, d);
+    }
+    return (uint32_t)hi;  // what remains is below B <= 2^32
 }
 
 __device__ __forceinline__ void put_le(uint8_t *p, uint64_t v, int bytes) {

@@ -35,23 +35,27 @@ struct Magic {
 // (s_0 = 1) every word i uses p_i = k if s_i <= Qk else k - 1, R_i = floor(Q_{p_i} / s_i),
 // and the next state is ceil(B / R_i). The state sequence is eventually periodic:
 // s_{i + lam} = s_i for i >= mu, so entries 0 .. mu+lam-1 describe every word.
-// Digits handled in 32-bit chunks: h digits per chunk with P = B^h < 2^32 and B^(h-1) < 2^24,
-// so a chunk is built by 24-bit multiply-adds and split from a word by one 64-bit magic
-// division by P; inside a chunk the digits come out by binary64 division by B (rB).
-// h = 0 when B >= 2^24 (digits then go one by one through 64-bit arithmetic).
+// Packing: digits handled in 32-bit chunks of h digits with P = B^h < 2^32 and B^(h-1) < 2^24,
+// so a chunk is built by 24-bit multiply-adds and joined to the word by one 64-bit multiply-add
+// (h = 0 when B >= 2^24: digits then go one by one through 64-bit arithmetic).
+// Unpacking: a word splits once, at P2 = B^h2 with h2 = max(1, floor(k / 2)), into two parts
+// below 2^51 (2^13 <= P2 <= 2^32); inside a part below 2^51 the digits come out by binary64
+// division by B (rB = 1 / B rounded to nearest).
 struct Chunk {
-    Magic mP;      // 64-bit division by P
-    uint32_t h;    // digits per chunk
+    uint32_t h;    // digits per packing chunk
     uint32_t P;    // B^h
     double rB;     // 1 / B rounded to nearest binary64
+    double P2;     // B^h2, exact
+    double rP2;    // 1 / P2 rounded to nearest binary64
+    uint32_t h2;   // digits below the split of a word
+    uint32_t pad;
 };
 
 struct BaseDesc {
     uint64_t Qk;   // floor(2^64 / B^k)
     uint64_t Qk1;  // floor(2^64 / B^(k-1))
-    Magic mB;      // division by B
     Magic mBp[2];  // division by B^(k-1) and by B^k (the latter unused when B^k = 2^64)
-    Chunk ch;      // 32-bit chunking of digits
+    Chunk ch;      // chunking of digits (packing and unpacking)
     uint32_t off;  // first AtlasEntry
     uint32_t V;    // values consumed by one cycle: q_{mu+lam} - q_mu
     uint16_t mu, lam;
@@ -70,6 +74,7 @@ struct DevTables {
     const BaseDesc *desc;    // [kAtlasBases]
     const AtlasEntry *ent;   // entries of every base
     const uint64_t *kmax;    // [65]: kmax[k] = largest B with B^k <= 2^64 (kmax[1] = UINT64_MAX)
+    const uint8_t *ktab;     // [kAtlasDirect + 1]: k(B) for every B <= 2^16 + 1 (0 for B < 2)
 };
 
 // Stream layout (mirrors the format described in pcomp.h).
@@ -113,26 +118,32 @@ __host__ __device__ inline void make_layout(uint64_t n, uint32_t w, uint32_t L, 
     lo.off_payload = (o + 7) & ~(uint64_t)7;
 }
 
-// One stream of a call: its values, where its stream sits in the output, and its tiles.
-// A batch is a table of these, grouped by element width (one group per launch); a single
-// call is a table of one. For decompression `data` is the destination of the values.
+// One stream of a call: its values, its layout and its tiles. A batch is a table of these,
+// grouped by element width (one group per launch); a single call is a table of one. For
+// decompression `data` is the destination of the values. Where a segment's stream starts in
+// the output is only known once every block is sized: compression computes it on the device
+// (placement launch), decompression reads it from the caller's offsets.
 struct SegDesc {
     const uint8_t *data;  // the segment's values (compress: read; decompress: written)
-    uint64_t out_off;     // byte offset of the segment's stream in the batch buffer (8-aligned)
     Layout lo;
     uint64_t tile0;       // global index of the segment's first tile
     uint32_t user;        // position of the segment in the caller's list
     uint32_t group;       // element-width group: 0 u8, 1 u16, 2 u32
+    // Time-major blocking (rows > 0): the values are matrices [rows][cols], row-major, and the
+    // stream holds each matrix's transpose: value t = (e cols + c) rows + r of the stream is
+    // element (e, r, c). rows = 0: the values are read in their own order.
+    uint32_t rows, cols;
 };
 
 // Host-built plan of a batch: this header, then n_segs SegDesc in group order (the groups'
-// global tiles are consecutive), then the segment of every global tile (u32 each).
+// global tiles are consecutive), then the segment of every global tile (u32 each, padded to
+// 8 bytes), then the plan index of every segment in the caller's order (u32 each).
 struct BatchPlanHeader {
     uint64_t magic;                  // kPlanMagic
     uint32_t n_segs;
     int32_t variant;
     uint64_t n_tiles;                // tiles of the whole batch
-    uint64_t out_bytes;              // batch buffer bytes: the sum of the segments' bounds
+    uint64_t out_cap;                // output bytes that always suffice: the sum of the segments' bounds
     uint64_t ws_bytes;               // workspace bytes
     uint64_t plan_bytes;             // bytes of the whole plan
     uint64_t tile_lo[3], tile_hi[3]; // global tiles of each group (0 u8, 1 u16, 2 u32)

@@ -48,12 +48,18 @@ def _check_batch(pc, orc, segs, block_len, variant, grid, what):
     b.compress()
     streams = b.streams()
     Ls = pc._block_lens(block_len)
+    wants = []
     for i, (x, s) in enumerate(zip(segs, streams)):
         L = Ls[{1: 0, 2: 1, 4: 2}[x.element_size()]]
         want = orc.compress(_as_np(x), L, variant)
         got = s.cpu().numpy().tobytes()
         assert got == want, "%s: segment %d (n=%d %s) stream differs (%d vs %d bytes)" % (
             what, i, x.numel(), x.dtype, len(got), len(want))
+        wants.append(want)
+    # the batch is one file: the oracle's streams back to back, in the segments' order
+    assert b.file().cpu().numpy().tobytes() == b"".join(wants), "%s: batch file differs" % what
+    offs = np.cumsum([0] + [len(w) for w in wants])[:-1].tolist()
+    assert b.offsets() == offs, "%s: stream offsets" % what
     outs = [torch.empty_like(d) for d in dev]
     dec = pc.BatchDecoder(b, outs, grid=grid)
     dec()
@@ -97,6 +103,8 @@ def test_batch_graph_replays(pc, orc):
     gen.manual_seed(5)
     for rep in range(3):
         print("case: graph replay", rep, flush=True)
+        b.total.zero_()
+        b.seg_offsets.fill_(-1)
         for d in dev:  # new values, same shapes, written eagerly
             if d.numel():
                 hi = {1: 255, 2: 4000, 4: 1 << 20}[d.element_size()]
@@ -106,10 +114,13 @@ def test_batch_graph_replays(pc, orc):
         g.replay()
         torch.cuda.synchronize()
         streams = b.streams()
+        wants = []
         for i, (d, s) in enumerate(zip(dev, streams)):
             L = (256, 512, 1024)[{1: 0, 2: 1, 4: 2}[d.element_size()]]
             want = orc.compress(_as_np(d), L, EXH)
             assert s.cpu().numpy().tobytes() == want, "replay %d segment %d" % (rep, i)
+            wants.append(want)
+        assert b.file().cpu().numpy().tobytes() == b"".join(wants), "replay %d: batch file" % rep
 
 
 def test_batch_decoder_reports_corrupt_header(pc, orc):
@@ -119,12 +130,19 @@ def test_batch_decoder_reports_corrupt_header(pc, orc):
     b.compress()
     torch.cuda.synchronize()
     buf = b.out.clone()
-    off = b.offsets[1]
+    off = b.offsets()[1]
     buf[off + 16] ^= 1  # n of the second stream no longer matches the plan
     outs = [torch.empty_like(d) for d in dev]
     dec = pc.BatchDecoder(b, outs)
     dec(buf)
     assert int(dec.status.item()) == pc.ECORRUPT
+    # an offset that is not a stream start (unaligned, or past the buffer) is reported too
+    # (segment 0 has values, so its stream is read)
+    for bad in (b.offsets()[0] + 4, b.out.numel() + 64):
+        offs = b.seg_offsets.clone()
+        offs[0] = bad
+        dec(b.out, offs)
+        assert int(dec.status.item()) == pc.ECORRUPT
 
 
 def test_autotuner_picks_valid_configuration(pc, orc, tmp_path, monkeypatch):

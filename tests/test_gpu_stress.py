@@ -1,6 +1,8 @@
 """Stress workload on the GPU: 4 GiB of mixed u8/u16/u32 blocks (Laplacian noise with scale
 U(1, 50), 0.1% outliers over the full range, constant and full-range blocks) plus one u32
-block for every base B in [2, 2^16], as one batch whose later streams start past 2^32 bytes.
+block for every base B in [2, 2^16], as one batch. The streams are packed one after another,
+and at a ratio of about 1.37 four GiB of input make 3.3 GB of streams; the test compresses 6 GiB
+so that the later streams start past 2^32 bytes.
 Every value round-trips on the GPU; sampled tiles equal the oracle's stream of the same
 blocks byte for byte (block arrays and payload)."""
 import numpy as np
@@ -52,17 +54,18 @@ def stress_segments(total_bytes: int = 1 << 32, seed: int = 90):
 
 
 def test_stress_4gib_batch(pc, orc):
-    segs = stress_segments()
+    segs = stress_segments(6 << 30)
     raw = sum(s.numel() * s.element_size() for s in segs)
     print("case: stress batch, %d segments, %.3f GB" % (len(segs), raw / 1e9), flush=True)
-    assert raw >= 1 << 32
+    assert raw >= 6 << 30
     b = pc.Batch(segs, block_len=L, variant=EXH)
-    assert b.offsets[-1] > 1 << 32  # the base sweep's stream sits past 2^32 bytes
     b.compress()
     torch.cuda.synchronize()
     assert b.error_flag() == 0
-    sizes = b.sizes.tolist()
-    print("ratio %.4f" % (raw / sum(sizes)), flush=True)
+    offs = b.offsets() + [b.total_bytes()]
+    assert offs[-2] > 1 << 32  # the base sweep's stream sits past 2^32 bytes
+    sizes = [offs[i + 1] - offs[i] for i in range(len(segs))]
+    print("ratio %.4f" % (raw / offs[-1]), flush=True)
     outs = [torch.empty_like(s) for s in segs]
     dec = pc.BatchDecoder(b, outs)
     dec()
@@ -73,7 +76,7 @@ def test_stress_4gib_batch(pc, orc):
     # sampled tiles against the oracle's stream of the same blocks
     rng = np.random.default_rng(5)
     for i, s in enumerate(segs):
-        st = b.out[b.offsets[i]:b.offsets[i] + sizes[i]]
+        st = b.out[offs[i]:offs[i] + sizes[i]]
         head = st[:64].cpu().numpy()
         meta0 = _parse(np.concatenate([head, np.zeros(0, np.uint8)]))
         nt = meta0["ntiles"]

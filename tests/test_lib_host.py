@@ -103,9 +103,10 @@ def _segs(pc, spec):
     return arr
 
 
-def test_batch_plan_slots_and_tiles(pc, orc):
-    """Streams sit in the caller's order, each in a slot of its bound; tiles are counted per
-    segment with the segment's own tile size."""
+def test_batch_plan_capacity_and_tiles(pc, orc):
+    """The output capacity of a batch is the sum of its segments' bounds (the streams, packed one
+    after another, never take more); tiles are counted per segment with the segment's own tile
+    size; the workspace holds one block record per tile slot of each width group."""
     spec = [(2, 74200), (4, 3000), (2, 0), (1, 777), (2, 1), (4, 50000), (1, 0)]
     Ls = (300, 40, 1000)
     for variant in (0, 8, 5, 0x100):
@@ -117,18 +118,17 @@ def test_batch_plan_slots_and_tiles(pc, orc):
         assert pc.lib().pcomp_batch_plan(segs, len(spec), L3, variant, buf, nb) == 0
         assert pc.lib().pcomp_batch_plan(segs, len(spec), L3, variant, buf, nb - 8) == pc.ENOSPC
         ob, wb, nt = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
-        offs = (ctypes.c_uint64 * len(spec))()
-        assert pc.lib().pcomp_batch_info(buf, ctypes.byref(ob), ctypes.byref(wb), ctypes.byref(nt), offs) == 0
-        off, tiles = 0, 0
+        assert pc.lib().pcomp_batch_info(buf, ctypes.byref(ob), ctypes.byref(wb), ctypes.byref(nt)) == 0
+        cap, tiles, slots = 0, 0, 0
         for i, (w, n) in enumerate(spec):
             L = Ls[{1: 0, 2: 1, 4: 2}[w]]
-            assert offs[i] == off
-            off += orc.bound(n, w, L, variant)
+            cap += orc.bound(n, w, L, variant)
             nblk = (n + L - 1) // L
             tb = orc.tile_blocks(L, w)
             tiles += (nblk + tb - 1) // tb
-        assert ob.value == off and nt.value == tiles
-        assert wb.value >= 8 + 12 * tiles
+            slots += (nblk + tb - 1) // tb * tb * (2 * w + 4)
+        assert ob.value == cap and nt.value == tiles
+        assert wb.value >= 8 + 12 * tiles + 8 * len(spec) + slots
 
 
 def test_batch_plan_rejects_bad_arguments(pc):
@@ -140,7 +140,7 @@ def test_batch_plan_rejects_bad_arguments(pc):
     # an unused group's block length is not checked
     assert pc.lib().pcomp_batch_plan_bytes(_segs(pc, [(1, 10)]), 1, big, 0) > 0
     buf = (ctypes.c_uint64 * 8)()
-    assert pc.lib().pcomp_batch_info(buf, None, None, None, None) == pc.EINVAL  # not a plan
+    assert pc.lib().pcomp_batch_info(buf, None, None, None) == pc.EINVAL  # not a plan
 
 
 def test_binding_rejects_host_tensors_and_bad_shapes(pc):
