@@ -85,9 +85,11 @@ typedef enum { PCOMP_U8 = 1, PCOMP_U16 = 2, PCOMP_U32 = 4 } pcomp_dtype;
 #define PCOMP_ENOMODEL (-4) /* learned selector requested with no model loaded */
 #define PCOMP_EHIP (-5)     /* a HIP runtime call or launch failed */
 #define PCOMP_ENOWS (-6)    /* workspace smaller than pcomp_workspace_size */
+#define PCOMP_ENOINIT (-7)  /* pcomp_compress_noalloc before pcomp_init on this device */
 
-/* One-time set-up of the constant tables on the current device. Optional;
- * thread-safe; returns PCOMP_OK or PCOMP_EHIP. */
+/* One-time set-up on the current device: the constant tables and the address
+ * of the device buffer pcomp_compress_noalloc uses. Optional for every other
+ * call; thread-safe; returns PCOMP_OK or PCOMP_EHIP. */
 int pcomp_init(void);
 
 /* Host-only, pure. Largest stream the compressor can write for these arguments:
@@ -117,6 +119,24 @@ size_t pcomp_workspace_size(uint64_t n, pcomp_dtype dtype, uint32_t block_len, i
 int pcomp_compress(const void *d_in, uint64_t n, pcomp_dtype dtype, uint32_t block_len, int variant,
                    void *d_out, size_t out_capacity, uint64_t *d_out_size, void *d_ws, size_t ws_bytes,
                    void *stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): pcomp_compress with
+ * its workspace taken from a buffer of PCOMP_SCRATCH_BYTES that the library
+ * holds in the global memory of every device it runs on, until the process
+ * ends. The call itself allocates nothing. Call pcomp_init() once on the
+ * device first (PCOMP_ENOINIT otherwise). Calls whose pcomp_workspace_size
+ * exceeds PCOMP_SCRATCH_BYTES return PCOMP_ENOWS (for u16 data in blocks of
+ * 40 values that is above about 160 million values; longer blocks allow
+ * more). Every call on one device shares that one buffer and leaves its last
+ * contents there (each call rewrites all it reads): calls that may overlap on
+ * one device (different streams or host threads) race, so the caller must
+ * order them. The first u32 of the buffer is the error word described under
+ * pcomp_compress. Other arguments, results and errors are those of
+ * pcomp_compress. */
+#define PCOMP_SCRATCH_BYTES (32u << 20)
+int pcomp_compress_noalloc(const void *d_in, uint64_t n, pcomp_dtype dtype, uint32_t block_len, int variant,
+                           void *d_out, size_t out_capacity, uint64_t *d_out_size, void *stream);
 
 /* Decompresses the v1 stream at d_in (in_size bytes, 8-byte aligned) into
  * d_out (capacity out_capacity values of the stream's dtype). *d_status

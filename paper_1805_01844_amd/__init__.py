@@ -17,9 +17,10 @@ LIB_PATH = os.path.join(HERE, "libpcomp.so")
 
 SELECT_EXHAUSTIVE = 0x100
 SELECT_LEARNED = 0x200
-OK, EINVAL, ENOSPC, ECORRUPT, ENOMODEL, EHIP, ENOWS = 0, -1, -2, -3, -4, -5, -6
+OK, EINVAL, ENOSPC, ECORRUPT, ENOMODEL, EHIP, ENOWS, ENOINIT = 0, -1, -2, -3, -4, -5, -6, -7
 _ERR = {EINVAL: "EINVAL", ENOSPC: "ENOSPC", ECORRUPT: "ECORRUPT", ENOMODEL: "ENOMODEL", EHIP: "EHIP",
-        ENOWS: "ENOWS"}
+        ENOWS: "ENOWS", ENOINIT: "ENOINIT"}
+SCRATCH_BYTES = 32 << 20  # PCOMP_SCRATCH_BYTES
 
 _DT = {torch.uint8: 1, torch.uint16: 2, torch.uint32: 4}
 _TORCH = {1: torch.uint8, 2: torch.uint16, 4: torch.uint32}
@@ -49,6 +50,8 @@ def lib():
         L.pcomp_workspace_size.argtypes = [u64, i32, u32, i32]
         L.pcomp_compress.restype = i32
         L.pcomp_compress.argtypes = [vp, u64, i32, u32, i32, vp, sz, vp, vp, sz, vp]
+        L.pcomp_compress_noalloc.restype = i32
+        L.pcomp_compress_noalloc.argtypes = [vp, u64, i32, u32, i32, vp, sz, vp, vp]
         L.pcomp_decompress.restype = i32
         L.pcomp_decompress.argtypes = [vp, sz, vp, sz, vp, vp]
         L.pcomp_decompress_typed.restype = i32

@@ -188,6 +188,13 @@ int tables_for_current_device(DevTables *out) {
     return PCOMP_OK;
 }
 
+bool tables_ready_for_current_device() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return false;
+    std::lock_guard<std::mutex> lk(g_mu);
+    return g_dev[dev].ready;
+}
+
 }  // namespace pcomp
 
 // Host-side introspection of the tables, for tests that need no GPU.

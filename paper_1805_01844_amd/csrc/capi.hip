@@ -1,4 +1,5 @@
 // capi.hip -- the C ABI declared in include/pcomp.h: argument checks, sizes, launches.
+#include <mutex>
 
 #include "pcomp_internal.h"
 
@@ -88,9 +89,26 @@ const BatchPlanHeader *plan_header(const void *h_plan) {
 
 }  // namespace
 
+// Workspace of pcomp_compress_noalloc: one buffer in every device's global memory, held until
+// the process ends. In host code `scratch` is only a host-side stand-in for the symbol: the
+// device address comes from hipGetSymbolAddress, once per device, in pcomp_init.
+static __device__ __align__(256) uint8_t scratch[PCOMP_SCRATCH_BYTES];
+static void *g_scratch_ptr[64];
+static std::mutex g_scratch_mu;
+
 extern "C" int pcomp_init(void) {
     DevTables t;
-    return tables_for_current_device(&t);
+    const int rc = tables_for_current_device(&t);
+    if (rc != PCOMP_OK) return rc;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return PCOMP_EHIP;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return PCOMP_EHIP;
+        g_scratch_ptr[dev] = ptr;
+    }
+    return PCOMP_OK;
 }
 
 extern "C" size_t pcomp_bound(uint64_t n, pcomp_dtype dtype, uint32_t block_len, int variant) {
@@ -144,6 +162,25 @@ extern "C" int pcomp_compress_transposed(const void *d_in, uint64_t n_mat, uint3
     if (n_mat > UINT64_MAX / per) return PCOMP_EINVAL;
     return compress_checked(d_in, n_mat * per, dtype, block_len, variant, d_out, out_capacity, d_out_size, d_ws,
                             ws_bytes, rows, cols, stream);
+}
+
+extern "C" int pcomp_compress_noalloc(const void *d_in, uint64_t n, pcomp_dtype dtype, uint32_t block_len,
+                                      int variant, void *d_out, size_t out_capacity, uint64_t *d_out_size,
+                                      void *stream) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return PCOMP_EHIP;
+    void *ptr;
+    {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        ptr = g_scratch_ptr[dev];
+    }
+    // pcomp_init has not run on this device: its tables and the buffer's address are missing,
+    // and setting them up here would allocate
+    if (!ptr || !tables_ready_for_current_device()) return PCOMP_ENOINIT;
+    const size_t need = pcomp_workspace_size(n, dtype, block_len, variant);
+    if (need > PCOMP_SCRATCH_BYTES) return PCOMP_ENOWS;
+    return pcomp_compress(d_in, n, dtype, block_len, variant, d_out, out_capacity, d_out_size, ptr,
+                          PCOMP_SCRATCH_BYTES, stream);
 }
 
 extern "C" int pcomp_decompress(const void *d_in, size_t in_size, void *d_out, size_t out_capacity,

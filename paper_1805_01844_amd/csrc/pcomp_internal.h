@@ -154,5 +154,7 @@ constexpr uint64_t kPlanMagic = 0x4E414C5042504350ull;  // "PCPBPLAN"
 
 // Host side: tables of the current device (built on first use).
 int tables_for_current_device(DevTables *out);
+// Host side: whether the current device's tables are built (nothing is allocated).
+bool tables_ready_for_current_device();
 
 }  // namespace pcomp
