@@ -100,7 +100,7 @@ size_t pcomp_bound(uint64_t n, pcomp_dtype dtype, uint32_t block_len, int varian
 
 /* Host-only, pure. Device workspace bytes that pcomp_compress needs (an error
  * word, size tables, three tables of advanced word counts for full blocks
- * (128 KiB each), per-tile word totals and their prefix sums, and one record
+ * (256 KiB each), per-tile word totals and their prefix sums, and one record
  * of 2 w + 4 bytes per block: min, B - 1, class, words and n_e, passed from
  * the sizing launch to the packing launch). Returns 0 for invalid args. */
 size_t pcomp_workspace_size(uint64_t n, pcomp_dtype dtype, uint32_t block_len, int variant);

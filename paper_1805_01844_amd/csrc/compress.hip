@@ -35,7 +35,7 @@ namespace pcomp {
 __constant__ float c_model[kMlpParams];
 constexpr uint32_t kFeatWords = 11;  // per block in LDS: 16 16-bit counts, min, max, L_b
 constexpr uint32_t kExcBytes = 2048;  // compaction buffer of a tile's excess lists
-constexpr uint32_t kAdvTab = kAtlasDirect + 1;  // entries of an advanced-count table (bases 0 .. 2^16 + 1)
+constexpr uint32_t kAdvTab = kAtlasDirect + 1;  // entries of a full-block word table (bases 0 .. 2^16 + 1)
 static_assert(kFeatWords * 4 * kMaxTileBlocks <= kTileBytes, "features must fit in the tile buffer");
 
 struct CompressArgs {
@@ -507,10 +507,20 @@ __global__ __launch_bounds__(kThreads) void stats_kernel(CompressArgs a) {
         // beat the best (words, id) key seen by the lane, so the classes it skips cannot win.
         uint64_t key = ~0ull;
         if (live && variant == PCOMP_SELECT_EXHAUSTIVE) {
-            uint32_t nwm;
-            key = (uint64_t)class_words<(W == 4)>(T, s_C, L, 0, Lb, B, beta, 0, nwm) << 8;
+            // classes 0 and 8: one load of the full-block table, else k(B) once for both families
+            uint32_t w0 = 0, w8 = 0;
+            if (B > 1 && Lb == L && s_C.fullW && B <= kAtlasDirect) {
+                const uint32_t fw = ((const __attribute__((address_space(1))) uint32_t *)s_C.fullW)[B];
+                w0 = fw & 0xFFFFu;
+                w8 = fw >> 16;
+            } else if (B > 1) {
+                const uint32_t kb = k_fast(s_C, B);
+                w0 = udiv_small(Lb + kb - 1, kb);
+                w8 = adv_words_k<(W == 4)>(T, s_C, Lb, B, kb, L);
+            }
+            key = (uint64_t)w0 << 8;
             if (beta >= 1) {
-                const uint64_t k8 = ((uint64_t)class_words<(W == 4)>(T, s_C, L, 8, Lb, B, beta, 0, nwm) << 8) | 8;
+                const uint64_t k8 = ((uint64_t)w8 << 8) | 8;
                 key = k8 < key ? k8 : key;
             }
             // lanes split the thresholds t; each sizes both families of its t, which share the
@@ -531,7 +541,7 @@ __global__ __launch_bounds__(kThreads) void stats_kernel(CompressArgs a) {
                 if (net && Be > 1) {
                     const uint32_t ke = k_fast(s_C, Be);
                     e0 = udiv_small(net + ke - 1, ke);
-                    e1 = net <= ke ? 1 : fam_words<(W == 4)>(T, s_C, 1, net, Be, L);
+                    e1 = adv_words_k<(W == 4)>(T, s_C, net, Be, ke, L);
                 }
                 const uint64_t k0 = ((uint64_t)(m0 + e0) << 8) | (uint64_t)t;
                 const uint64_t k1 = ((uint64_t)(m1 + e1) << 8) | (uint64_t)(8 + t);
@@ -833,27 +843,32 @@ __global__ __launch_bounds__(kThreads) void pack_kernel(CompressArgs a) {
 // ---- launch 1: per-call preparation --------------------------------------------------------
 // Clears the error word and fills the size tables of the three width groups (block length L[g]).
 __global__ __launch_bounds__(kThreads) void prep_kernel(CompressArgs a, SizeCtx *ctx, uint32_t L0, uint32_t L1,
-                                                         uint32_t L2, const uint16_t *adv_tab) {
+                                                         uint32_t L2, const uint32_t *adv_tab) {
     const uint32_t Ls[3] = {L0, L1, L2};
     for (int g = 0; g < 3; g++)
         if (Ls[g]) fill_size_ctx(a.T, Ls[g], ctx[g], adv_tab ? adv_tab + (size_t)g * kAdvTab : nullptr);
     if (threadIdx.x == 0) *a.err = 0;
 }
 
-// Advanced word counts of a full block (L digits) for every base B <= 2^16 + 1, per call and
-// width group: the statistics and packing launches read them instead of searching the
-// series of each block.
-__global__ __launch_bounds__(kThreads) void adv_table_kernel(DevTables T, uint32_t L, uint16_t *tab) {
+// Words of a full block (L digits) for every base B <= 2^16 + 1, basic (bits 0-15) and advanced
+// (bits 16-31), per call and width group: the statistics launch reads both family sizes of a
+// block with one load instead of sizing them, and the series of no block is searched.
+__global__ __launch_bounds__(kThreads) void adv_table_kernel(DevTables T, uint32_t L, uint32_t *tab) {
     const uint32_t B = blockIdx.x * kThreads + threadIdx.x;
     if (B >= kAdvTab) return;
-    tab[B] = B < 2 ? 0 : (uint16_t)adv_words_atlas(T, T.desc[B], L);
+    if (B < 2) {
+        tab[B] = 0;
+        return;
+    }
+    const BaseDesc &D = T.desc[B];
+    tab[B] = udiv_small(L + D.k - 1, D.k) | ((uint32_t)adv_words_atlas(T, D, L) << 16);
 }
 
 // Workspace: [err u32, 0 u32][3 size tables, kCtxBytes each][3 advanced-count tables of
-// kAdvTab u16, padded to 8 bytes][one u32 word total per tile, padded to 8 bytes][one u64
+// kAdvTab u32][one u32 word total per tile, padded to 8 bytes][one u64
 // prefix per tile, then their sum][one u64 sum per run of kScanTiles tiles][one u64 stream
 // offset per segment][the block records of each width group].
-constexpr uint64_t kAdvTabBytes = 3 * ((2ull * kAdvTab + 7) & ~7ull);
+constexpr uint64_t kAdvTabBytes = 3 * ((4ull * kAdvTab + 7) & ~7ull);
 struct WsLayout {
     uint64_t ctx, adv, tile_words, prefix, sums, seg_off, rec[3], rec_n[3], bytes;
 };
@@ -927,7 +942,7 @@ int launch_compress_table(const SegDesc *segs, const uint32_t *tile_seg, const u
     a.total = d_total;
     a.err = (uint32_t *)wsb;
     SizeCtx *ctx = (SizeCtx *)(wsb + wl.ctx);
-    uint16_t *adv_tab = (uint16_t *)(wsb + wl.adv);
+    uint32_t *adv_tab = (uint32_t *)(wsb + wl.adv);
     a.tile_words = (uint32_t *)(wsb + wl.tile_words);
     a.prefix = (uint64_t *)(wsb + wl.prefix);
     uint64_t *sums = (uint64_t *)(wsb + wl.sums);

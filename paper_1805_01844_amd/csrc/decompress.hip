@@ -1,13 +1,14 @@
 // decompress.hip -- grid-stride decompression kernel (gfx950).
 //
 // The stream's tile index gives every tile its payload offset, so tiles decode
-// independently. Per tile: the block arrays are read into LDS and every block's word count
-// is recomputed from (L_b, B, class, n_e); the lanes of a block's group decode its words in
-// turn, peeling digits from the lowest power by multiply-high magic-number division (the
-// inverse polynomial division of Sec. 3.1); for the advanced method the value split
-// between word i (r_i) and word i+1 (r'_i on top) is rebuilt by the lane of word i from
-// both words; threshold blocks merge their excess list back in data order; the tile leaves
-// LDS through coalesced stores.
+// independently. Per tile: every block's word count is recomputed from its arrays (L_b, B,
+// class, n_e); the lanes of a block's group decode its words, peeling digits from the lowest
+// power (the inverse polynomial division of Sec. 3.1; see peel_digits); for the advanced method
+// the value split between word i (r_i) and word i+1 (r'_i on top) is rebuilt from both words;
+// threshold blocks merge their excess list back in data order; the tile leaves LDS through
+// coalesced stores. A workgroup walks its tiles with loads ahead of use: while one tile's
+// values are merged and stored, the next tile's block arrays come into registers and its first
+// payload words straight into LDS (global_load_lds), so decoding waits on no payload load.
 #include "kernels_common.h"
 
 namespace pcomp {
@@ -64,11 +65,13 @@ __device__ bool read_layout(const uint8_t *in, uint64_t in_size, Layout &lo, uin
     return true;
 }
 
-constexpr uint32_t kDecExcBytes = 8192;
+constexpr uint32_t kDecExcBytes = 2048;
+constexpr uint32_t kDecWords = 512;  // payload words of a tile staged in LDS before its decoding
 
 struct DecShared {
     uint4 raw[kTileBytes / 16];  // decoded digits / values of the tile
     uint4 exc[kDecExcBytes / 16];  // decoded excess lists of the tile, when they fit
+    uint64_t words[kDecWords];     // the tile's first payload words
     uint16_t exoff[kMaxTileBlocks];  // each threshold block's place among the tile's excess values
     uint32_t min[kMaxTileBlocks], rng[kMaxTileBlocks], ne[kMaxTileBlocks];
     uint32_t nwm[kMaxTileBlocks], off[kMaxTileBlocks + 1];
@@ -82,9 +85,9 @@ struct DecShared {
 // Advanced part whose base is outside the tables: each lane of the group walks the series
 // itself (the state of word i depends on every word before it) and decodes its own words
 // i0, i0 + G, ... (G a power of two), including the value split at the end of each.
-template <typename V, typename Dst>
+template <typename V, typename Src, typename Dst>
 __device__ __forceinline__ void unpack_adv_slow(const DevTables &T, uint64_t base, uint32_t n, uint32_t nwords,
-                                                uint32_t i0, uint32_t G, const uint64_t *src, Dst dst, uint32_t add) {
+                                                uint32_t i0, uint32_t G, Src src, Dst dst, uint32_t add) {
     const SlowBase sb = slow_base(T, base);
     const Magic mB = magic_dev(base);
     uint32_t q = 0, p;
@@ -97,7 +100,7 @@ __device__ __forceinline__ void unpack_adv_slow(const DevTables &T, uint64_t bas
         if (!last) slow_word_fast(sb, slow_next(sb, R), p1, R1);
         if (((wi - i0) & (G - 1)) == 0 && wi >= i0) {
             uint64_t r;
-            uint64_t X = udiv64_48(src[wi], R, r);  // word = (r'_{i-1} B^p + digits) R + r
+            uint64_t X = udiv64_48(src(wi), R, r);  // word = (r'_{i-1} B^p + digits) R + r
             for (int j = (int)p - 1; j >= 0; j--) {
                 const uint64_t qq = div_magic(X, mB);
                 if (q + j < n) dst[q + j] = (V)((uint32_t)(X - qq * base) + add);
@@ -105,7 +108,7 @@ __device__ __forceinline__ void unpack_adv_slow(const DevTables &T, uint64_t bas
             }
             if (!last) {  // r'_i sits on top of the next word, above its p_{i+1} digits
                 uint64_t r1;
-                uint64_t Y = udiv64_48(src[wi + 1], R1, r1);
+                uint64_t Y = udiv64_48(src(wi + 1), R1, r1);
                 for (uint32_t m = 0; m < p1; m++) Y = div_magic(Y, mB);
                 dst[q + p] = (V)((uint32_t)(Y * R + r) + add);
             }
@@ -118,10 +121,11 @@ __device__ __forceinline__ void unpack_adv_slow(const DevTables &T, uint64_t bas
 }
 
 // Decodes words i0, i0+G, ... of one part (main digits or excess list) into dst[0 .. n);
-// `add` is added to every digit (the block minimum for plain blocks).
-template <typename V, bool Wide, bool kRuns, typename Dst>
+// `add` is added to every digit (the block minimum for plain blocks); src(i) is word i of the
+// part.
+template <typename V, bool Wide, bool kRuns, typename Src, typename Dst>
 __device__ __forceinline__ void unpack_part(const DevTables &T, const PartBase &pb, uint32_t n, int fam,
-                                            uint32_t nwords, uint32_t i0, uint32_t G, const uint64_t *src, Dst dst,
+                                            uint32_t nwords, uint32_t i0, uint32_t G, Src src, Dst dst,
                                             uint32_t add) {
     if (nwords == 0 || i0 >= nwords) return;
     auto put = [&](uint32_t j, uint32_t d) {
@@ -135,9 +139,9 @@ __device__ __forceinline__ void unpack_part(const DevTables &T, const PartBase &
         // The next word's load is in flight while a word is peeled.
         const uint32_t k = pb.k;
         uint32_t i = i0;
-        uint64_t w = src[i];
+        uint64_t w = src(i);
         for (; i + 1 < nwords; i += G) {
-            const uint64_t wn = i + G < nwords ? src[i + G] : 0;
+            const uint64_t wn = i + G < nwords ? src(i + G) : 0;
             peel_digits<Wide>(pb, w, i * k, k, put_all);
             w = wn;
         }
@@ -151,7 +155,7 @@ __device__ __forceinline__ void unpack_part(const DevTables &T, const PartBase &
         for (uint32_t i = i0; i < nwords; i += G) {
             uint32_t q;
             const AtlasEntry *e = adv_entry(T, D, i, q);
-            const uint64_t X = src[i];
+            const uint64_t X = src(i);
             const uint64_t qR = div_magic(X, e->mR);
             const uint64_t r = X - qR * e->R;  // r_i, the low part of the split value
             const uint32_t p = e->p;
@@ -164,7 +168,7 @@ __device__ __forceinline__ void unpack_part(const DevTables &T, const PartBase &
             if (q + p < n && i + 1 < nwords) {
                 uint32_t q1;
                 const AtlasEntry *e1 = adv_entry(T, D, i + 1, q1);
-                const uint64_t Y = div_magic(src[i + 1], e1->mR);
+                const uint64_t Y = div_magic(src(i + 1), e1->mR);
                 const uint64_t rp = div_magic(Y, D.mBp[e1->p == D.k ? 1 : 0]);
                 put(q + p, (uint32_t)(rp * e->R + r));
             }
@@ -183,7 +187,7 @@ __device__ __forceinline__ void unpack_part(const DevTables &T, const PartBase &
         uint32_t q = 0, p = 0;
         for (uint32_t i = w0; i < w1; i++) {
             const AtlasEntry *e = adv_entry(T, D, i, q);
-            const uint64_t X = src[i];
+            const uint64_t X = src(i);
             const uint64_t qR = div_magic(X, e->mR);
             const uint64_t r = X - qR * e->R;  // r_i, the low part of the next split value
             p = e->p;
@@ -198,7 +202,7 @@ __device__ __forceinline__ void unpack_part(const DevTables &T, const PartBase &
         if (w0 < w1 && w1 < nwords && q + p < n) {
             uint32_t q1;
             const AtlasEntry *e1 = adv_entry(T, D, w1, q1);
-            const uint64_t Y = div_magic(src[w1], e1->mR);
+            const uint64_t Y = div_magic(src(w1), e1->mR);
             const uint64_t rp = div_magic(Y, D.mBp[e1->p == D.k ? 1 : 0]);
             put(q + p, (uint32_t)(rp * R_prev + r_prev));
         }
@@ -208,48 +212,104 @@ __device__ __forceinline__ void unpack_part(const DevTables &T, const PartBase &
     if (Wide) unpack_adv_slow<V>(T, pb.base, n, nwords, i0, G, src, dst, add);
 }
 
+// Block arrays of block b of a tile, held by thread b from their load to their use.
+struct BlockRaw {
+    uint32_t bmin, rng, cne;  // min, B - 1, class | n_e << 8
+};
+
+template <int W>
+__device__ __forceinline__ BlockRaw load_raw(const uint8_t *in, const Layout &lo, int fixed, uint64_t tile) {
+    BlockRaw r = {0, 0, 0};
+    const uint64_t b0 = tile * lo.tile_blocks;
+    if (threadIdx.x < min((uint64_t)lo.tile_blocks, lo.n_blocks - b0)) {
+        const uint64_t gb = b0 + threadIdx.x;
+        const int neb = (lo.flags & kFlagNe16) ? 2 : 1;
+        r.bmin = (uint32_t)get_le(in + lo.off_min + gb * W, W);
+        r.rng = (uint32_t)get_le(in + lo.off_range + gb * W, W);
+        const uint32_t c = (lo.flags & kFlagClass) ? in[lo.off_class + gb] : (uint32_t)fixed;
+        const uint32_t ne = (lo.flags & kFlagNe) ? (uint32_t)get_le(in + lo.off_ne + gb * neb, neb) : 0;
+        r.cne = (c & 0xFF) | (ne << 8);
+    }
+    return r;
+}
+
+// Where a tile's payload starts and ends (payload words), from the index; an inconsistent pair
+// leaves the tile with nothing to stage (it is reported corrupt when decoded).
+struct TileSpan {
+    uint64_t base, next;
+    uint32_t staged;  // words of the tile in S.words
+};
+
+__device__ __forceinline__ TileSpan tile_span(const uint8_t *in, const Layout &lo, uint64_t pw, uint64_t tile) {
+    // scalar loads (the stream is read-only during the call): the entries stay out of vector
+    // registers, and waiting for them does not wait for the vector memory operations
+    const __attribute__((address_space(4))) uint64_t *idx =
+        (const __attribute__((address_space(4))) uint64_t *)(in + lo.off_index);
+    TileSpan t;
+    t.base = idx[tile];
+    t.next = tile + 1 < lo.n_tiles ? idx[tile + 1] : pw;
+    const bool ok = t.base <= t.next && t.next <= pw;
+    t.staged = ok ? (uint32_t)min(t.next - t.base, (uint64_t)kDecWords) : 0;
+    return t;
+}
+
+// Starts copying the tile's first payload words into S.words, straight from global memory to
+// LDS (one dword per lane and instruction; the wavefront's lanes fill consecutive dwords). The
+// copy is complete once the issuing wavefront's vector-memory counter is zero.
+__device__ __forceinline__ void stage_words(const uint8_t *in, const Layout &lo, const TileSpan &t, DecShared &S) {
+    const uint32_t ndw = 2 * t.staged;
+    const uint32_t *g = (const uint32_t *)(in + lo.off_payload) + 2 * t.base;
+    uint32_t *l = (uint32_t *)S.words + (threadIdx.x & ~63u);
+    for (uint32_t c = 0; c < ndw; c += kThreads)
+        if (c + threadIdx.x < ndw)
+            __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)(g + c + threadIdx.x),
+                                             (__attribute__((address_space(3))) void *)(l + c), 4, 0, 0);
+}
+
+// s_waitcnt vmcnt(0): this wavefront's vector-memory operations are complete (direct-to-LDS
+// copies included).
+__device__ __forceinline__ void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
 // Decodes tile `tile` of the stream at `in` (layout lo, pw payload words, fixed class of a
-// single-class stream) into out. Every thread of the workgroup calls it.
-template <int W, bool kRuns, bool kTm = false>
+// single-class stream) into out. Every thread of the workgroup calls it, with its block's arrays
+// (raw) and the tile's span, whose first words are being copied to S.words. `ahead` runs once the
+// tile's words are no longer read (it may start the next tile's loads).
+template <int W, bool kRuns, bool kTm = false, typename Ahead>
 __device__ __forceinline__ void decode_tile(const DevTables &T, const uint8_t *in, const Layout &lo, uint64_t pw,
-                                            int fixed, uint64_t tile, uint8_t *out, int32_t *status, DecShared &S,
-                                            uint32_t rows = 0, uint32_t cols = 0) {
+                                            uint64_t tile, const BlockRaw &raw, const TileSpan &span, uint8_t *out,
+                                            int32_t *status, DecShared &S, Ahead ahead, uint32_t rows = 0,
+                                            uint32_t cols = 0) {
     typedef typename Elem<W>::T V;
     const uint32_t tid = threadIdx.x;
     const uint32_t L = lo.L, tb = lo.tile_blocks;
     const uint32_t G = kThreads / tb;
-    const uint64_t *idx = (const uint64_t *)(in + lo.off_index);
     const uint64_t *payload_all = (const uint64_t *)(in + lo.off_payload);
     const uint64_t vmaxw = (1ull << (8 * W)) - 1;
     V *s_val = (V *)S.raw;
-    const int neb = (lo.flags & kFlagNe16) ? 2 : 1;
     {
         const uint64_t b0 = tile * tb;
         const uint32_t nbt = (uint32_t)min((uint64_t)tb, lo.n_blocks - b0);
         const uint64_t v0 = b0 * L;
         const uint32_t nvt = (uint32_t)min((uint64_t)nbt * L, lo.n - v0);
-        // ---- 1. block arrays of the tile and word counts (the tile's index entries are
-        //         fetched at once, alongside). One scan of packed fields gives each block its
-        //         word offset, its place among the tile's excess values and its lane group
+        // ---- 1. word counts from the block arrays. One scan of packed fields gives each block
+        //         its word offset, its place among the tile's excess values and its lane group
         //         (basic blocks first, then advanced ones, so that wavefronts mostly run one
         //         family's code), and counts blocks with invalid fields.
-        const uint64_t base_off = idx[tile];
-        const uint64_t next_off = (tile + 1 < lo.n_tiles) ? idx[tile + 1] : pw;
+        const uint64_t base_off = span.base, next_off = span.next;
         uint64_t key = 0;
         bool adv = false;
         if (tid < nbt) {
             const uint64_t gb = b0 + tid;
-            const uint32_t bmin = (uint32_t)get_le(in + lo.off_min + gb * W, W);
-            const uint32_t rng = (uint32_t)get_le(in + lo.off_range + gb * W, W);
-            const int c = (lo.flags & kFlagClass) ? in[lo.off_class + gb] : fixed;
-            const uint32_t ne = (lo.flags & kFlagNe) ? (uint32_t)get_le(in + lo.off_ne + gb * neb, neb) : 0;
+            const uint32_t bmin = raw.bmin, rng = raw.rng;
+            const int c = (int)(raw.cne & 0xFF);
+            const uint32_t ne = raw.cne >> 8;
             const uint32_t Lb = (uint32_t)min((uint64_t)L, lo.n - gb * L);
             const uint64_t B = (uint64_t)rng + 1;
             const uint32_t beta = bitlen64(B - 1);
             const int t = c & 7;
             bool ok = c < 16 && t <= (int)beta && ne <= Lb && (t != 0 || ne == 0) && (uint64_t)bmin + rng <= vmaxw;
             uint32_t nwm = 0, nw = 0;
-            if (ok) nw = class_words<(W == 4)>(T, S.C, L, c, Lb, B, beta, ne, nwm);
+            if (ok) nw = class_words<(W == 4), false>(T, S.C, L, c, Lb, B, beta, ne, nwm);
             ok = ok && nw <= 2 * Lb;  // each part takes at most one word per value
             if (!ok) nw = nwm = 0;
             S.min[tid] = bmin;
@@ -273,13 +333,19 @@ __device__ __forceinline__ void decode_tile(const DevTables &T, const uint8_t *i
             S.perm[adv ? n_basic + (uint32_t)((ex >> 45) & 0x1FF) : (uint32_t)((ex >> 36) & 0x1FF)] = (uint8_t)tid;
         }
         if (tid == 0) S.off[nbt] = tile_words;
+        wait_vmem();  // this wavefront's share of the staged words is in LDS
         __syncthreads();
         if (n_bad || base_off > pw || next_off > pw || next_off != base_off + tile_words) {
             if (tid == 0) set_status(status, PCOMP_ECORRUPT);
+            ahead();
             __syncthreads();
             return;
         }
-        const uint64_t *payload = payload_all + base_off;
+        const uint32_t staged = span.staged;
+        const __attribute__((address_space(1))) uint64_t *payload =
+            (const __attribute__((address_space(1))) uint64_t *)(payload_all + base_off);
+        // word wi of the tile: from LDS if staged, else from global memory
+        auto word_at = [&](uint32_t wi) -> uint64_t { return wi < staged ? S.words[wi] : payload[wi]; };
         // decoded excess digits go to LDS when they fit, else to the tile's own output range,
         // which nothing reads or writes until the final store of the tile
         // (the two places are kept apart in the code, so that each access uses its own address space)
@@ -297,24 +363,30 @@ __device__ __forceinline__ void decode_tile(const DevTables &T, const uint8_t *i
             const int t = c & 7, fam = c >> 3;
             const uint64_t B = (uint64_t)S.rng[blk] + 1;
             const uint32_t Lb = (uint32_t)min((uint64_t)L, lo.n - (b0 + blk) * L);
-            const uint64_t *src = payload + S.off[blk];
+            const uint32_t w0 = S.off[blk];
+            auto src = [&](uint32_t i) -> uint64_t { return word_at(w0 + i); };
+            // the basic family's constants come from the base alone; the advanced family reads
+            // the schedule of its series from the tables
+            auto base_of = [&](uint64_t base) -> PartBase {
+                return fam ? resolve_base<(W == 4)>(T, S.C, base) : basic_base(S.C, base);
+            };
             V *vals = s_val + (size_t)blk * L;
             if (t == 0) {
-                unpack_part<V, (W == 4), kRuns>(T, resolve_base<(W == 4)>(T, S.C, B), Lb, fam, nwb, g, G, src, vals,
-                                         S.min[blk]);
+                unpack_part<V, (W == 4), kRuns>(T, base_of(B), Lb, fam, nwb, g, G, src, vals, S.min[blk]);
             } else {
                 const uint64_t Th = 1ull << (bitlen64(B - 1) - t);
                 const uint32_t nwm = S.nwm[blk];
-                unpack_part<V, (W == 4), kRuns>(T, resolve_base<(W == 4)>(T, S.C, Th + 1), Lb, fam, nwm, g, G, src, vals,
-                                         S.min[blk]);
-                const PartBase pe = resolve_base<(W == 4)>(T, S.C, B - Th);
+                unpack_part<V, (W == 4), kRuns>(T, base_of(Th + 1), Lb, fam, nwm, g, G, src, vals, S.min[blk]);
+                const PartBase pe = base_of(B - Th);
+                auto esrc = [&](uint32_t i) -> uint64_t { return word_at(w0 + nwm + i); };
                 if (exc_lds)
-                    unpack_part<V, (W == 4), kRuns>(T, pe, S.ne[blk], fam, nwb - nwm, g, G, src + nwm, l_exc + S.exoff[blk], 0);
+                    unpack_part<V, (W == 4), kRuns>(T, pe, S.ne[blk], fam, nwb - nwm, g, G, esrc, l_exc + S.exoff[blk], 0);
                 else
-                    unpack_part<V, (W == 4), kRuns>(T, pe, S.ne[blk], fam, nwb - nwm, g, G, src + nwm, g_exc + S.exoff[blk], 0);
+                    unpack_part<V, (W == 4), kRuns>(T, pe, S.ne[blk], fam, nwb - nwm, g, G, esrc, g_exc + S.exoff[blk], 0);
             }
         }
         __syncthreads();
+        ahead();  // the staged words are no longer read
 
         // ---- 3. threshold blocks: a main value equal to min + T (digit T) marks the next excess
         //         value, which is added to it. Blocks with B = 1 have no words: every value is
@@ -485,8 +557,35 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(W == 4
     }
     fill_size_ctx(a.T, lo.L, S.C);
     __syncthreads();
-    for (uint64_t tile = blockIdx.x; tile < lo.n_tiles; tile += gridDim.x)
-        decode_tile<W, kRuns, kTm>(a.T, a.in, lo, pw, fixed, tile, a.out, a.status, S, a.rows, a.cols);
+    // Tiles tile, tile + grid, ...: the next tile's arrays and words are started while this one
+    // is merged and stored, and the index entries one tile further ahead.
+    uint64_t tile = blockIdx.x;
+    if (tile >= lo.n_tiles) return;
+    BlockRaw raw = load_raw<W>(a.in, lo, fixed, tile);
+    TileSpan span = tile_span(a.in, lo, pw, tile);
+    stage_words(a.in, lo, span, S);
+    uint64_t nxt = tile + gridDim.x;
+    TileSpan nspan = nxt < lo.n_tiles ? tile_span(a.in, lo, pw, nxt) : span;
+    for (;;) {
+        const bool more = nxt < lo.n_tiles;
+        const uint64_t nxt2 = nxt + gridDim.x;
+        BlockRaw nraw = raw;
+        TileSpan nnspan = nspan;
+        auto ahead = [&]() {
+            if (more) {
+                stage_words(a.in, lo, nspan, S);
+                nraw = load_raw<W>(a.in, lo, fixed, nxt);
+                if (nxt2 < lo.n_tiles) nnspan = tile_span(a.in, lo, pw, nxt2);
+            }
+        };
+        decode_tile<W, kRuns, kTm>(a.T, a.in, lo, pw, tile, raw, span, a.out, a.status, S, ahead, a.rows, a.cols);
+        if (!more) break;
+        tile = nxt;
+        raw = nraw;
+        span = nspan;
+        nspan = nnspan;
+        nxt = nxt2;
+    }
 }
 
 // Batch: the tiles of one width group, each decoded into its segment's destination. A
@@ -510,7 +609,11 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(W == 4
             if (threadIdx.x == 0) set_status(a.status, PCOMP_ECORRUPT);
             continue;
         }
-        decode_tile<W, kRuns>(a.T, s, lo, pw, fixed, gt - sd.tile0, (uint8_t *)sd.data, a.status, S);
+        const uint64_t tile = gt - sd.tile0;
+        const BlockRaw raw = load_raw<W>(s, lo, fixed, tile);
+        const TileSpan span = tile_span(s, lo, pw, tile);
+        stage_words(s, lo, span, S);
+        decode_tile<W, kRuns>(a.T, s, lo, pw, tile, raw, span, (uint8_t *)sd.data, a.status, S, [] {});
     }
 }
 

@@ -195,13 +195,15 @@ struct SizeCtx {
     uint64_t kmax[65];
     uint32_t p1_k[32];
     uint32_t p1_adv[32];
-    const uint16_t *advL;  // advanced words of a full block for every base <= 2^16 + 1, or nullptr
+    uint32_t p1_basic[32];  // basic words of a full block of base 2^j + 1
+    // per base B <= 2^16 + 1: words of a full block, basic (bits 0-15) and advanced (16-31), or nullptr
+    const uint32_t *fullW;
     const uint8_t *ktab;   // k(B) for every base <= 2^16 + 1
 };
 
-__device__ inline void fill_size_ctx(const DevTables &T, uint32_t L, SizeCtx &C, const uint16_t *advL = nullptr) {
+__device__ inline void fill_size_ctx(const DevTables &T, uint32_t L, SizeCtx &C, const uint32_t *fullW = nullptr) {
     const uint32_t t = threadIdx.x;
-    if (t == 200) C.advL = advL;
+    if (t == 200) C.fullW = fullW;
     if (t == 201) C.ktab = T.ktab;
     if (t < 65) C.kmax[t] = T.kmax[t];
     if (t >= 96 && t < 128) {
@@ -209,13 +211,17 @@ __device__ inline void fill_size_ctx(const DevTables &T, uint32_t L, SizeCtx &C,
         const BaseDesc &D = T.desc[atlas_index((1ull << j) + 1)];
         C.p1_k[j] = D.k;
         C.p1_adv[j] = adv_words_atlas(T, D, L);
+        C.p1_basic[j] = udiv_small(L + D.k - 1, D.k);
     }
 }
 
-// k(B) = max{k : B^k <= 2^64} for B >= 2 (Sec. 3.1 Eq. (1), exact reading), from a float
-// estimate corrected against the exact table.
+// k(B) = max{k : B^k <= 2^64} for B >= 2 (Sec. 3.1 Eq. (1), exact reading). kTab: bases up to
+// 2^16 + 1 from the per-device table in global memory (one load); otherwise, and for larger
+// bases, a float estimate corrected against the exact bounds in LDS (no global load: the
+// decoder, whose tiles wait on every load, takes this way).
+template <bool kTab = true>
 __device__ __forceinline__ uint32_t k_fast(const SizeCtx &C, uint64_t B) {
-    if (B <= kAtlasDirect) return ((const __attribute__((address_space(1))) uint8_t *)C.ktab)[B];  // global, not flat
+    if (kTab && B <= kAtlasDirect) return ((const __attribute__((address_space(1))) uint8_t *)C.ktab)[B];  // global, not flat
     uint32_t k = (uint32_t)(64.0f * __builtin_amdgcn_rcpf(__log2f((float)B)));  // corrected below
     k = k < 1 ? 1 : (k > 63 ? 63 : k);
     const uint64_t cur = C.kmax[k], up = C.kmax[k + 1];  // both bounds fetched together
@@ -232,15 +238,15 @@ __device__ __forceinline__ uint32_t k_fast(const SizeCtx &C, uint64_t B) {
 // Words of family fam (0 basic Sec. 3.1, 1 advanced Sec. 3.2) for n digits of `base`;
 // `full` is the block length L (a block of n == L values can use the cache). Wide: the data
 // are u32, so a base can lie outside the tables (u8 and u16 bases never do).
-template <bool Wide>
+template <bool Wide, bool kTab = true>
 __device__ inline uint32_t fam_words(const DevTables &T, const SizeCtx &C, int fam, uint32_t n, uint64_t base,
                                      uint32_t full) {
     if (n == 0 || base <= 1) return 0;
-    const uint32_t k = k_fast(C, base);
+    const uint32_t k = k_fast<kTab>(C, base);
     if (!fam) return udiv_small(n + k - 1, k);
     if (n <= k) return 1;
-    if (n == full && C.advL && base <= kAtlasDirect)
-        return ((const __attribute__((address_space(1))) uint16_t *)C.advL)[base];  // global, not flat
+    if (n == full && C.fullW && base <= kAtlasDirect)
+        return ((const __attribute__((address_space(1))) uint32_t *)C.fullW)[base] >> 16;  // global, not flat
     const uint64_t bm1 = base - 1;
     if ((bm1 & (bm1 - 1)) == 0 && n == full) return C.p1_adv[bitlen64(bm1) - 1];  // base 2^j + 1
     const int ai = atlas_index(base);
@@ -251,22 +257,34 @@ __device__ inline uint32_t fam_words(const DevTables &T, const SizeCtx &C, int f
 
 // Words of the main part (digits min(d, T) in base T + 1, T = 2^(beta - t)) of a threshold
 // class, t >= 1: a lower bound of the class's words.
-template <bool Wide>
+template <bool Wide, bool kTab = true>
 __device__ __forceinline__ uint32_t main_words(const DevTables &T, const SizeCtx &C, uint32_t L, int fam, int t,
                                                uint32_t Lb, uint32_t beta) {
     const uint32_t j = beta - t;
-    if (!fam) return udiv_small(Lb + C.p1_k[j] - 1, C.p1_k[j]);
-    return (Lb == L) ? C.p1_adv[j] : fam_words<Wide>(T, C, 1, Lb, (1ull << j) + 1, L);
+    if (!fam) return Lb == L ? C.p1_basic[j] : udiv_small(Lb + C.p1_k[j] - 1, C.p1_k[j]);
+    return (Lb == L) ? C.p1_adv[j] : fam_words<Wide, kTab>(T, C, 1, Lb, (1ull << j) + 1, L);
+}
+
+// Advanced words of n digits of `base` once its k is known: one word for n <= k, else the
+// series' bounds ceil((n+1)/(k+1)) <= words <= ceil(n/k) (every word after the first takes k
+// or k + 1 values), and the series itself only where they differ.
+template <bool Wide>
+__device__ __forceinline__ uint32_t adv_words_k(const DevTables &T, const SizeCtx &C, uint32_t n, uint64_t base,
+                                                uint32_t k, uint32_t full) {
+    if (n <= k) return 1;
+    const uint32_t lo = udiv_small(n + 1 + k, k + 1), hi = udiv_small(n + k - 1, k);
+    if (lo == hi) return lo;
+    return fam_words<Wide>(T, C, 1, n, base, full);
 }
 
 // Words of class c = 8 family + t for a block of Lb digits of base B (beta = bitlen(B-1));
 // ne_t = digits >= T = 2^(beta - t). nw_main receives the main-part words.
-template <bool Wide>
+template <bool Wide, bool kTab = true>
 __device__ inline uint32_t class_words(const DevTables &T, const SizeCtx &C, uint32_t L, int c, uint32_t Lb,
                                        uint64_t B, uint32_t beta, uint32_t ne_t, uint32_t &nw_main) {
     const int fam = c >> 3, t = c & 7;
     if (t == 0) {
-        nw_main = fam_words<Wide>(T, C, fam, Lb, B, L);
+        nw_main = fam_words<Wide, kTab>(T, C, fam, Lb, B, L);
         return nw_main;
     }
     const uint32_t j = beta - t;
@@ -274,8 +292,8 @@ __device__ inline uint32_t class_words(const DevTables &T, const SizeCtx &C, uin
     if (!fam)
         nw_main = udiv_small(Lb + C.p1_k[j] - 1, C.p1_k[j]);
     else
-        nw_main = (Lb == L) ? C.p1_adv[j] : fam_words<Wide>(T, C, 1, Lb, Th + 1, L);
-    return nw_main + fam_words<Wide>(T, C, fam, ne_t, B - Th, L);
+        nw_main = (Lb == L) ? C.p1_adv[j] : fam_words<Wide, kTab>(T, C, 1, Lb, Th + 1, L);
+    return nw_main + fam_words<Wide, kTab>(T, C, fam, ne_t, B - Th, L);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -399,6 +417,37 @@ struct PartBase {
     Chunk ch;             // chunking (packing h = 0: digit by digit in 64 bits)
     const BaseDesc *D;    // schedule of the advanced series, nullptr outside the tables
 };
+
+// B^e by squaring, for B^e <= 2^53: every factor used (B^(2^i) with 2^i <= e) and every partial
+// product is at most B^e, so each multiplication is exact.
+__host__ __device__ __forceinline__ double pow_exact(double B, uint32_t e) {
+    double P = 1.0, sq = B;
+    for (;;) {
+        if (e & 1) P *= sq;
+        e >>= 1;
+        if (!e) break;
+        sq *= sq;
+    }
+    return P;
+}
+
+// The decoder's constants of a basic-family part, from the base alone (no table load): k(B)
+// from the bounds in LDS, h2, B^h2 by squaring (every power used is at most 2^32, exact in
+// binary64), and the correctly rounded reciprocals of IEEE division.
+__device__ __forceinline__ PartBase basic_base(const SizeCtx &C, uint64_t base) {
+    PartBase pb;
+    pb.base = base;
+    pb.k = k_fast<false>(C, base);
+    pb.ch.h = 0;
+    pb.ch.P = 0;
+    pb.ch.h2 = pb.k / 2 > 1 ? pb.k / 2 : 1;
+    const double Bf = (double)base;
+    pb.ch.rB = 1.0 / Bf;
+    pb.ch.P2 = pow_exact(Bf, pb.ch.h2);
+    pb.ch.rP2 = 1.0 / pb.ch.P2;
+    pb.D = nullptr;
+    return pb;
+}
 
 template <bool Wide>
 __device__ __forceinline__ PartBase resolve_base(const DevTables &T, const SizeCtx &C, uint64_t base) {

@@ -27,7 +27,8 @@ FILTERS = {
     "fast": [{"id": lzma.FILTER_LZMA2, "preset": 1, "nice_len": 64, "dict_size": 32 << 20}],
     "best": [{"id": lzma.FILTER_LZMA2, "preset": 9, "nice_len": 64, "dict_size": 192 << 20}],
 }
-CHUNK = 32 << 20  # bytes per independently compressed LZMA member
+CHUNK = 4 << 20  # largest independently compressed LZMA member (bytes)
+MIN_CHUNK = 1 << 18
 
 _MAGIC = b"PLZ1"
 
@@ -36,9 +37,17 @@ def _threads(threads):
     return max(1, int(threads if threads else (os.cpu_count() or 1)))
 
 
-def lzma_pack(data: bytes, mode: str = "fast", threads: int = 0, chunk: int = CHUNK) -> bytes:
-    """LZMA of `data` in independent chunks: magic, chunk count, the compressed size of every
-    chunk (u64 each), then the chunks."""
+def chunk_for(n: int, threads: int = 0) -> int:
+    """Member size for n bytes: enough members for every host thread, each between MIN_CHUNK and
+    CHUNK bytes."""
+    t = _threads(threads)
+    return min(CHUNK, max(MIN_CHUNK, -(-n // t)))
+
+
+def lzma_pack(data: bytes, mode: str = "fast", threads: int = 0, chunk: int = 0) -> bytes:
+    """LZMA of `data` in independent chunks (chunk = 0: ``chunk_for``): magic, chunk count, the
+    compressed size of every chunk (u64 each), then the chunks."""
+    chunk = chunk if chunk > 0 else chunk_for(len(data), threads)
     parts = [data[i:i + chunk] for i in range(0, len(data), chunk)] or [b""]
 
     def one(p):
@@ -67,10 +76,10 @@ def lzma_unpack(blob: bytes, threads: int = 0) -> bytes:
     return b"".join(parts)
 
 
-def compress(stream: torch.Tensor, mode: str = "fast", threads: int = 0) -> bytes:
+def compress(stream: torch.Tensor, mode: str = "fast", threads: int = 0, chunk: int = 0) -> bytes:
     """Second stage: LZMA of a polynomial stream (a u8 tensor on the GPU or the host)."""
     host = stream.detach().to("cpu", non_blocking=False).contiguous()
-    return lzma_pack(host.numpy().tobytes(), mode, threads)
+    return lzma_pack(host.numpy().tobytes(), mode, threads, chunk)
 
 
 def decompress(blob: bytes, device="cuda", threads: int = 0) -> torch.Tensor:

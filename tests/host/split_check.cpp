@@ -34,7 +34,12 @@ static int check(uint64_t B, uint64_t X, int full) {
     const uint32_t h2 = k / 2 > 1 ? k / 2 : 1;
     uint64_t P = 1;
     for (uint32_t i = 0; i < h2; i++) P *= B;
-    const double Pd = (double)P, rP = 1.0 / (double)P;
+    const double Pd = pcomp::pow_exact((double)B, h2), rP = 1.0 / Pd;
+    cases++;
+    if (Pd != (double)P) {
+        printf("power mismatch B=%llu h2=%u\n", (unsigned long long)B, h2);
+        return 1;
+    }
     double hi, lo;
     pcomp::split_word(X, Pd, rP, hi, lo);
     cases++;
