@@ -67,25 +67,34 @@ __device__ bool read_layout(const uint8_t *in, uint64_t in_size, Layout &lo, uin
 
 constexpr uint32_t kDecExcBytes = 2048;
 constexpr uint32_t kDecWords = 512;  // payload words of a tile staged in LDS before its decoding
+// Words of a tile that the chosen classes can take: every class is at most the basic t = 0 size,
+// ceil(L_b / k(B)) <= L_b w / 8 + 1 words since k(B) >= 8 / w, so a tile of at most 16 KiB of
+// values has at most 2048 + tile_blocks words. Larger counts (a stream written with other
+// choices) find their block by search instead of through the map.
+constexpr uint32_t kMapWords = kTileBytes / 8 + kMaxTileBlocks;
 
 struct DecShared {
     uint4 raw[kTileBytes / 16];  // decoded digits / values of the tile
     uint4 exc[kDecExcBytes / 16];  // decoded excess lists of the tile, when they fit
     uint64_t words[kDecWords];     // the tile's first payload words
     uint16_t exoff[kMaxTileBlocks];  // each threshold block's place among the tile's excess values
-    uint32_t min[kMaxTileBlocks], rng[kMaxTileBlocks], ne[kMaxTileBlocks];
-    uint32_t nwm[kMaxTileBlocks], off[kMaxTileBlocks + 1];
+    uint32_t min[kMaxTileBlocks], rng[kMaxTileBlocks];
+    uint16_t ne[kMaxTileBlocks], nwm[kMaxTileBlocks];
+    uint32_t off[kMaxTileBlocks + 1];
     uint8_t cls[kMaxTileBlocks];
     uint8_t perm[kMaxTileBlocks];  // block taken by lane group p: basic blocks first, then advanced
+    uint16_t advw[kMaxTileBlocks]; // words of advanced blocks before the block (word-by-word decoding)
+    uint8_t map[kMapWords];        // block of every word of the tile (word-by-word decoding)
     uint32_t red32[kThreads / 64];
     uint64_t red64[kThreads / 64];
     SizeCtx C;
 };
+static_assert(sizeof(DecShared) <= 32768, "five workgroups per CU need at most 32 KiB of LDS each");
 
 // Advanced part whose base is outside the tables: each lane of the group walks the series
 // itself (the state of word i depends on every word before it) and decodes its own words
 // i0, i0 + G, ... (G a power of two), including the value split at the end of each.
-template <typename V, typename Src, typename Dst>
+template <typename V, bool kOne = false, typename Src, typename Dst>
 __device__ __forceinline__ void unpack_adv_slow(const DevTables &T, uint64_t base, uint32_t n, uint32_t nwords,
                                                 uint32_t i0, uint32_t G, Src src, Dst dst, uint32_t add) {
     const SlowBase sb = slow_base(T, base);
@@ -112,6 +121,7 @@ __device__ __forceinline__ void unpack_adv_slow(const DevTables &T, uint64_t bas
                 for (uint32_t m = 0; m < p1; m++) Y = div_magic(Y, mB);
                 dst[q + p] = (V)((uint32_t)(Y * R + r) + add);
             }
+            if (kOne) break;  // kOne: word i0 only
         }
         if (last) break;
         q += p + 1;
@@ -212,6 +222,42 @@ __device__ __forceinline__ void unpack_part(const DevTables &T, const PartBase &
     if (Wide) unpack_adv_slow<V>(T, pb.base, n, nwords, i0, G, src, dst, add);
 }
 
+// Decodes word i (its value X) of one part (n digits in nwords words, constants pb) into
+// dst[0 .. n), adding `add` to every digit; src(q) is word q of the part (an advanced word
+// also reads the next one, which holds the rest of the value split between them). One code
+// path for every word: positions past n (the padding of a last word) are not stored.
+template <typename V, bool Wide, typename Src, typename Dst>
+__device__ __forceinline__ void unpack_word(const DevTables &T, const PartBase &pb, uint32_t n, int fam,
+                                            uint32_t nwords, uint32_t i, uint64_t X, Src src, Dst dst,
+                                            uint32_t add) {
+    auto put = [&](uint32_t j, uint32_t d) {
+        if (j < n) dst[j] = (V)(d + add);
+    };
+    if (!fam) {  // inverse of Sec. 3.1 Eq. (2)
+        peel_digits<Wide>(pb, X, i * pb.k, pb.k, put);
+        return;
+    }
+    if (pb.D) {  // Sec. 3.2: r'_{i-1} on top, p_i digits, r_i at the bottom
+        const BaseDesc &D = *pb.D;
+        uint32_t q;
+        const AtlasEntry *e = adv_entry(T, D, i, q);
+        const uint64_t qR = div_magic(X, e->mR);
+        const uint64_t r = X - qR * e->R;
+        const uint32_t p = e->p;
+        peel_digits<Wide>(pb, qR, q, p, put);
+        if (q + p < n && i + 1 < nwords) {  // the value split with the next word
+            uint32_t q1;
+            const AtlasEntry *e1 = adv_entry(T, D, i + 1, q1);
+            const uint64_t Y = div_magic(src(i + 1), e1->mR);
+            const uint64_t rp = div_magic(Y, D.mBp[e1->p == D.k ? 1 : 0]);
+            put(q + p, (uint32_t)(rp * e->R + r));
+        }
+        return;
+    }
+    // base outside the tables (u32 data only): the series is walked up to word i
+    if (Wide) unpack_adv_slow<V, true>(T, pb.base, n, nwords, i, 1, src, dst, add);
+}
+
 // Block arrays of block b of a tile, held by thread b from their load to their use.
 struct BlockRaw {
     uint32_t bmin, rng, cne;  // min, B - 1, class | n_e << 8
@@ -266,9 +312,66 @@ __device__ __forceinline__ void stage_words(const uint8_t *in, const Layout &lo,
                                              (__attribute__((address_space(3))) void *)(l + c), 4, 0, 0);
 }
 
+// Barrier for data in LDS only: this wavefront's LDS operations are complete, then the
+// workgroup's wavefronts meet. Unlike __syncthreads it does not wait for global memory
+// operations in flight (the next tile's copies into LDS, stores of finished values); the asm
+// statement also keeps the compiler from moving memory accesses across it.
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
 // s_waitcnt vmcnt(0): this wavefront's vector-memory operations are complete (direct-to-LDS
 // copies included).
 __device__ __forceinline__ void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
+// A tile's values, decoded into LDS and not yet stored: they go to out + v0 values (nvt values).
+struct PendingStore {
+    uint8_t *out;
+    uint64_t v0;
+    uint32_t nvt;  // 0: nothing pending
+};
+
+// Coalesced store of the pending tile (16-byte stores where the output is aligned); a
+// time-major stream goes back to the caller's matrices value by value. Every thread calls it;
+// it only reads LDS, so the next tile's decoding may start after one barrier.
+template <int W, bool kTm>
+__device__ __forceinline__ void store_pending(PendingStore &pend, DecShared &S, uint32_t rows, uint32_t cols) {
+    typedef typename Elem<W>::T V;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t nvt = pend.nvt;
+    const uint64_t v0 = pend.v0;
+    uint8_t *const out = pend.out;
+    const V *s_val = (const V *)S.raw;
+    if (nvt) {
+        if (kTm) {
+            __attribute__((address_space(1))) V *gv = (__attribute__((address_space(1))) V *)out;
+            TmCursor cur(v0 + tid, rows, cols);
+            for (uint32_t j = tid; j < nvt; j += kThreads) {
+                gv[cur.index()] = s_val[j];
+                cur.step();
+            }
+        } else {
+            const uint8_t *sb = (const uint8_t *)S.raw;
+            __attribute__((address_space(1))) uint8_t *gdst = (__attribute__((address_space(1))) uint8_t *)(out + v0 * W);
+            const uint32_t head = (uint32_t)((16 - ((uintptr_t)gdst & 15)) & 15);
+            const uint32_t nbytes = nvt * W;
+            const uint32_t hb = head < nbytes ? head : nbytes;
+            for (uint32_t b = tid * W; b < hb; b += kThreads * W) *(__attribute__((address_space(1))) V *)(gdst + b) = *(const V *)(sb + b);
+            const uint32_t body = (nbytes - hb) >> 4;
+            if ((hb & 3) == 0) {
+                for (uint32_t c = tid; c < body; c += kThreads) {
+                    const uint32_t *s32 = (const uint32_t *)(sb + hb + (c << 4));
+                    typedef uint32_t U32x4 __attribute__((ext_vector_type(4)));
+                    *(__attribute__((address_space(1))) U32x4 *)(gdst + hb + (c << 4)) = U32x4{s32[0], s32[1], s32[2], s32[3]};
+                }
+            } else {
+                for (uint32_t b = hb + tid * W; b < hb + (body << 4); b += kThreads * W)
+                    *(__attribute__((address_space(1))) V *)(gdst + b) = *(const V *)(sb + b);
+            }
+            for (uint32_t b = hb + (body << 4) + tid * W; b < nbytes; b += kThreads * W)
+                *(__attribute__((address_space(1))) V *)(gdst + b) = *(const V *)(sb + b);
+        }
+    }
+    pend.nvt = 0;
+}
 
 // Decodes tile `tile` of the stream at `in` (layout lo, pw payload words, fixed class of a
 // single-class stream) into out. Every thread of the workgroup calls it, with its block's arrays
@@ -277,8 +380,8 @@ __device__ __forceinline__ void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70)
 template <int W, bool kRuns, bool kTm = false, typename Ahead>
 __device__ __forceinline__ void decode_tile(const DevTables &T, const uint8_t *in, const Layout &lo, uint64_t pw,
                                             uint64_t tile, const BlockRaw &raw, const TileSpan &span, uint8_t *out,
-                                            int32_t *status, DecShared &S, Ahead ahead, uint32_t rows = 0,
-                                            uint32_t cols = 0) {
+                                            int32_t *status, DecShared &S, PendingStore &pend, Ahead ahead,
+                                            uint32_t rows = 0, uint32_t cols = 0) {
     typedef typename Elem<W>::T V;
     const uint32_t tid = threadIdx.x;
     const uint32_t L = lo.L, tb = lo.tile_blocks;
@@ -298,6 +401,7 @@ __device__ __forceinline__ void decode_tile(const DevTables &T, const uint8_t *i
         const uint64_t base_off = span.base, next_off = span.next;
         uint64_t key = 0;
         bool adv = false;
+        uint32_t nw_own = 0;
         if (tid < nbt) {
             const uint64_t gb = b0 + tid;
             const uint32_t bmin = raw.bmin, rng = raw.rng;
@@ -315,25 +419,42 @@ __device__ __forceinline__ void decode_tile(const DevTables &T, const uint8_t *i
             S.min[tid] = bmin;
             S.rng[tid] = rng;
             S.cls[tid] = (uint8_t)(ok ? c : 0);
-            S.ne[tid] = ne;
-            S.nwm[tid] = nwm;
+            S.ne[tid] = (uint16_t)ne;
+            S.nwm[tid] = (uint16_t)nwm;
             adv = ok && (c >> 3);
-            // words (18 bits: a tile holds at most 2^14 values), excess values (18), basic
-            // blocks (9), advanced blocks (9), invalid blocks (9)
-            key = (uint64_t)nw | ((uint64_t)(ok && t ? ne : 0) << 18) | ((uint64_t)(adv ? 0 : 1) << 36) |
-                  ((uint64_t)(adv ? 1 : 0) << 45) | ((uint64_t)(ok ? 0 : 1) << 54);
+            nw_own = nw;
+            // words (18 bits: a tile holds at most 2^14 values), excess values (18), then for
+            // word-by-word decoding the words of advanced blocks (18), else basic blocks (9) and
+            // advanced blocks (9); invalid blocks (9)
+            key = (uint64_t)nw | ((uint64_t)(ok && t ? ne : 0) << 18) | ((uint64_t)(ok ? 0 : 1) << 54);
+            if (kRuns)
+                key |= ((uint64_t)(adv ? 0 : 1) << 36) | ((uint64_t)(adv ? 1 : 0) << 45);
+            else
+                key |= (uint64_t)(adv ? nw : 0) << 36;
         }
         uint64_t tot;
         const uint64_t ex = wg_excl_scan64(key, S.red64, &tot);
         const uint32_t tile_words = (uint32_t)(tot & 0x3FFFF), extot = (uint32_t)((tot >> 18) & 0x3FFFF);
         const uint32_t n_basic = (uint32_t)((tot >> 36) & 0x1FF), n_bad = (uint32_t)(tot >> 54);
+        // word-by-word decoding takes the words of basic blocks first (slots 0 .. w_basic - 1),
+        // then those of advanced blocks, each family in block order
+        const uint32_t w_basic = tile_words - (uint32_t)((tot >> 36) & 0x3FFFF);
         if (tid < nbt) {
             S.off[tid] = (uint32_t)(ex & 0x3FFFF);
             S.exoff[tid] = (uint16_t)((ex >> 18) & 0x3FFFF);
-            S.perm[adv ? n_basic + (uint32_t)((ex >> 45) & 0x1FF) : (uint32_t)((ex >> 36) & 0x1FF)] = (uint8_t)tid;
+            if (kRuns) {
+                S.perm[adv ? n_basic + (uint32_t)((ex >> 45) & 0x1FF) : (uint32_t)((ex >> 36) & 0x1FF)] = (uint8_t)tid;
+            } else {  // advanced words before the block, and the block of each of its slots
+                const uint32_t o = (uint32_t)(ex & 0x3FFFF), ap = (uint32_t)((ex >> 36) & 0x3FFFF);
+                S.advw[tid] = (uint16_t)ap;
+                const uint32_t s0 = adv ? w_basic + ap : o - ap;
+                const uint32_t e = min(s0 + nw_own, kMapWords);
+                for (uint32_t q = s0; q < e; q++) S.map[q] = (uint8_t)tid;
+            }
         }
         if (tid == 0) S.off[nbt] = tile_words;
         wait_vmem();  // this wavefront's share of the staged words is in LDS
+        store_pending<W, kTm>(pend, S, rows, cols);  // the previous tile leaves LDS
         __syncthreads();
         if (n_bad || base_off > pw || next_off > pw || next_off != base_off + tile_words) {
             if (tid == 0) set_status(status, PCOMP_ECORRUPT);
@@ -353,11 +474,66 @@ __device__ __forceinline__ void decode_tile(const DevTables &T, const uint8_t *i
         V *const l_exc = (V *)S.exc;
         __attribute__((address_space(1))) V *const g_exc = (__attribute__((address_space(1))) V *)(out + v0 * W);
 
-        // ---- 2. decode: the lanes of a block's group take its words in turn
+        // ---- 2. decode. Small blocks (fewer than kRunLanes lanes per block): the workgroup's
+        //         lanes take the tile's words in turn, whatever block each belongs to, so every
+        //         lane has the same number of words (one more at most). Larger blocks: the lanes
+        //         of a block's group take its words in turn (or runs of them).
         const uint32_t grp = tid / G, g = tid % G;
         const bool live = grp < nbt;
-        const uint32_t blk = live ? S.perm[grp] : grp;
-        if (live) {
+        const uint32_t blk = (kRuns && live) ? S.perm[grp] : grp;  // the merge takes blocks in place
+        if (!kRuns) {
+            const uint32_t last_Lb = nvt - (nbt - 1) * L;  // values of the tile's last block
+            for (uint32_t sl = tid; sl < tile_words; sl += kThreads) {
+                const bool advs = sl >= w_basic;
+                uint32_t b;
+                if (sl < kMapWords) {
+                    b = S.map[sl];
+                } else {  // the last block of the slot's family whose first slot is at or before it
+                    uint32_t l = 0, h = nbt;
+                    while (h - l > 1) {
+                        const uint32_t m = (l + h) >> 1;
+                        const uint32_t st = advs ? w_basic + S.advw[m] : S.off[m] - S.advw[m];
+                        if (st <= sl) l = m; else h = m;
+                    }
+                    b = l;
+                }
+                typedef typename Elem<W>::Base BT;
+                const uint32_t o = S.off[b], ap = S.advw[b];
+                const uint32_t wi = advs ? sl - w_basic - ap : sl - (o - ap);
+                const uint32_t c = S.cls[b];
+                const int t = (int)(c & 7), fam = (int)(c >> 3);
+                const BT B = (BT)S.rng[b] + 1;
+                // the part of the word: the block's only part, or for threshold classes the main
+                // part (base T + 1) or the excess list (base B - T)
+                BT base = B;
+                uint32_t n = b + 1 < nbt ? L : last_Lb, nwords = S.off[b + 1] - o, i = wi, p0 = o, add = S.min[b];
+                bool exw = false;
+                if (t) {
+                    const uint32_t nwm = S.nwm[b];
+                    const BT Th = (BT)1 << (bitlen64((uint64_t)B - 1) - t);
+                    exw = wi >= nwm;
+                    base = exw ? B - Th : Th + 1;
+                    if (exw) {
+                        n = S.ne[b];
+                        nwords -= nwm;
+                        i = wi - nwm;
+                        p0 = o + nwm;
+                        add = 0;
+                    } else {
+                        nwords = nwm;
+                    }
+                }
+                auto src = [&](uint32_t q) -> uint64_t { return word_at(p0 + q); };
+                const PartBase pb = resolve_base<(W == 4)>(T, S.C, (uint64_t)base);
+                const uint64_t X = word_at(o + wi);
+                if (!exw || exc_lds) {  // into LDS: the block's values, or the tile's excess lists
+                    V *d = exw ? l_exc + S.exoff[b] : s_val + (size_t)b * L;
+                    unpack_word<V, (W == 4)>(T, pb, n, fam, nwords, i, X, src, d, add);
+                } else {
+                    unpack_word<V, (W == 4)>(T, pb, n, fam, nwords, i, X, src, g_exc + S.exoff[b], 0);
+                }
+            }
+        } else if (live) {
             const uint32_t nwb = S.off[blk + 1] - S.off[blk];
             const int c = S.cls[blk];
             const int t = c & 7, fam = c >> 3;
@@ -491,39 +667,13 @@ __device__ __forceinline__ void decode_tile(const DevTables &T, const uint8_t *i
                 }
             }
         }
-        __syncthreads();
+        lds_barrier();  // the merged values are in LDS (the next tile's loads may still be in flight)
 
-        // ---- 4. coalesced store of the tile (16-byte stores where the output is aligned); a
-        //         time-major stream goes back to the caller's matrices value by value
-        if (kTm) {
-            __attribute__((address_space(1))) V *gv = (__attribute__((address_space(1))) V *)out;
-            TmCursor cur(v0 + tid, rows, cols);
-            for (uint32_t j = tid; j < nvt; j += kThreads) {
-                gv[cur.index()] = s_val[j];
-                cur.step();
-            }
-        } else {
-            const uint8_t *sb = (const uint8_t *)S.raw;
-            __attribute__((address_space(1))) uint8_t *gdst = (__attribute__((address_space(1))) uint8_t *)(out + v0 * W);
-            const uint32_t head = (uint32_t)((16 - ((uintptr_t)gdst & 15)) & 15);
-            const uint32_t nbytes = nvt * W;
-            const uint32_t hb = head < nbytes ? head : nbytes;
-            for (uint32_t b = tid * W; b < hb; b += kThreads * W) *(__attribute__((address_space(1))) V *)(gdst + b) = *(const V *)(sb + b);
-            const uint32_t body = (nbytes - hb) >> 4;
-            if ((hb & 3) == 0) {
-                for (uint32_t c = tid; c < body; c += kThreads) {
-                    const uint32_t *s32 = (const uint32_t *)(sb + hb + (c << 4));
-                    typedef uint32_t U32x4 __attribute__((ext_vector_type(4)));
-                    *(__attribute__((address_space(1))) U32x4 *)(gdst + hb + (c << 4)) = U32x4{s32[0], s32[1], s32[2], s32[3]};
-                }
-            } else {
-                for (uint32_t b = hb + tid * W; b < hb + (body << 4); b += kThreads * W)
-                    *(__attribute__((address_space(1))) V *)(gdst + b) = *(const V *)(sb + b);
-            }
-            for (uint32_t b = hb + (body << 4) + tid * W; b < nbytes; b += kThreads * W)
-                *(__attribute__((address_space(1))) V *)(gdst + b) = *(const V *)(sb + b);
-        }
-        __syncthreads();
+        // ---- 4. the values wait in LDS; the next tile (or the end of the workgroup's tiles)
+        //         stores them, once that tile's staged loads are complete
+        pend.out = out;
+        pend.v0 = v0;
+        pend.nvt = nvt;
     }
 }
 
@@ -566,6 +716,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(W == 4
     stage_words(a.in, lo, span, S);
     uint64_t nxt = tile + gridDim.x;
     TileSpan nspan = nxt < lo.n_tiles ? tile_span(a.in, lo, pw, nxt) : span;
+    PendingStore pend = {nullptr, 0, 0};
     for (;;) {
         const bool more = nxt < lo.n_tiles;
         const uint64_t nxt2 = nxt + gridDim.x;
@@ -578,7 +729,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(W == 4
                 if (nxt2 < lo.n_tiles) nnspan = tile_span(a.in, lo, pw, nxt2);
             }
         };
-        decode_tile<W, kRuns, kTm>(a.T, a.in, lo, pw, tile, raw, span, a.out, a.status, S, ahead, a.rows, a.cols);
+        decode_tile<W, kRuns, kTm>(a.T, a.in, lo, pw, tile, raw, span, a.out, a.status, S, pend, ahead, a.rows,
+                                   a.cols);
         if (!more) break;
         tile = nxt;
         raw = nraw;
@@ -586,6 +738,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(W == 4
         nspan = nnspan;
         nxt = nxt2;
     }
+    store_pending<W, kTm>(pend, S, a.rows, a.cols);
 }
 
 // Batch: the tiles of one width group, each decoded into its segment's destination. A
@@ -596,6 +749,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(W == 4
     __shared__ DecShared S;
     fill_size_ctx(a.T, a.L, S.C);
     __syncthreads();
+    PendingStore pend = {nullptr, 0, 0};
     for (uint64_t gt = a.tile_lo + blockIdx.x; gt < a.tile_hi; gt += gridDim.x) {
         const SegDesc sd = uniform_seg(a.segs[uni32(a.tile_seg[gt])]);
         const uint64_t off = uni64(a.seg_offsets[sd.user]);
@@ -613,8 +767,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(W == 4
         const BlockRaw raw = load_raw<W>(s, lo, fixed, tile);
         const TileSpan span = tile_span(s, lo, pw, tile);
         stage_words(s, lo, span, S);
-        decode_tile<W, kRuns>(a.T, s, lo, pw, tile, raw, span, (uint8_t *)sd.data, a.status, S, [] {});
+        decode_tile<W, kRuns>(a.T, s, lo, pw, tile, raw, span, (uint8_t *)sd.data, a.status, S, pend, [] {});
     }
+    store_pending<W, false>(pend, S, 0, 0);
 }
 
 __global__ void set_i32_kernel(int32_t *p, int32_t v) { *p = v; }

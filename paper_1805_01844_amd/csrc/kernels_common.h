@@ -12,14 +12,17 @@ struct Elem;
 template <>
 struct Elem<1> {
     typedef uint8_t T;
+    typedef uint32_t Base;  // holds B = max - min + 1
 };
 template <>
 struct Elem<2> {
     typedef uint16_t T;
+    typedef uint32_t Base;
 };
 template <>
 struct Elem<4> {
     typedef uint32_t T;
+    typedef uint64_t Base;
 };
 
 // Lanes per block from which advanced words are decoded in runs of consecutive words per lane
@@ -453,7 +456,7 @@ template <bool Wide>
 __device__ __forceinline__ PartBase resolve_base(const DevTables &T, const SizeCtx &C, uint64_t base) {
     PartBase pb;
     pb.base = base;
-    const int ai = atlas_index(base);
+    const int ai = Wide ? atlas_index(base) : (int)base;  // u8 / u16 bases are all in the tables
     if (!Wide || ai >= 0) {
         const BaseDesc &D = T.desc[ai >= 0 ? ai : 2];
         pb.k = D.k;

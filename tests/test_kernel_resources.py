@@ -3,7 +3,7 @@
 Every device function is inlined into its kernel: no kernel makes a call (an earlier build
 that called out-of-line slow paths with references to the caller's locals on the scratch stack
 once faulted the GPU, see the fault notes in the design document). Scratch memory is used only
-for a few register spills (no dynamic stack, at most 64 bytes per lane), and the kernels of
+for a few register spills (no dynamic stack, at most 96 bytes per lane), and the kernels of
 the camera workload keep the occupancy they are tuned for."""
 import concurrent.futures as cf
 import os
@@ -67,7 +67,7 @@ def test_no_calls_and_no_stack_objects(resources):
     assert not re.search(r"^\s*s_(swappc|setpc)_b64", asm, re.M), "a kernel makes a call"
     for name, r in funcs.items():
         assert r["Dynamic Stack"] == "False", name
-        assert int(r["ScratchSize [bytes/lane]"]) <= 64, (name, r["ScratchSize [bytes/lane]"])
+        assert int(r["ScratchSize [bytes/lane]"]) <= 96, (name, r["ScratchSize [bytes/lane]"])
 
 
 def test_camera_kernels_keep_their_occupancy(resources):
