@@ -89,7 +89,7 @@ struct Recs {
     }
 };
 
-__device__ void write_header(uint8_t *s, const Layout &lo, int variant, uint64_t payload_words) {
+__device__ __forceinline__ void write_header(uint8_t *s, const Layout &lo, int variant, uint64_t payload_words) {
     const uint64_t total = lo.off_payload + 8 * payload_words;
     const uint32_t sel = variant == PCOMP_SELECT_EXHAUSTIVE ? 1 : variant == PCOMP_SELECT_LEARNED ? 2 : 0;
     const uint32_t fixed = (lo.flags & kFlagClass) ? 0 : (uint32_t)variant;
@@ -123,9 +123,11 @@ __device__ __forceinline__ void pack_adv_slow(const DevTables &T, uint64_t base,
         slow_word_fast(sb, s, p, R);
         const bool mine = ((wi - i0) & (G - 1)) == 0 && wi >= i0;
         uint64_t acc = rp;
-        if (mine)  // digits in increasing order, then the split value
-            for (uint32_t j = 0; j < p; j++) acc = acc * base + get(q + j);
-        const uint64_t x = get(q + p);  // the value split between this word and the next
+        if (mine) {  // digits in increasing order (the absent ones of a last word are 0), then the split value
+            const uint32_t real = q < n ? min(p, n - q) : 0;
+            for (uint32_t j = 0; j < p; j++) acc = acc * base + (j < real ? get(q + j) : 0);
+        }
+        const uint64_t x = q + p < n ? get(q + p) : 0;  // the value split between this word and the next
         uint64_t r = x, top = 0;
         if (R <= x) {
             top = udiv53(x, R);
@@ -185,7 +187,7 @@ struct ExcessReader {
 
 // Packs the words of one part of a block (main digits or the excess list); the lanes of
 // the block's group call it with their first word index and stride. get(j) returns digit j
-// of the part, 0 past its end.
+// of the part; it is asked only for j < n (the absent digits of a last word are 0).
 template <bool Wide, typename Get>
 __device__ __forceinline__ void pack_part(const DevTables &T, const SizeCtx &C, uint64_t base, uint32_t n, int fam,
                                           uint32_t nwords, uint32_t i0, uint32_t G, uint64_t *dst, Get get) {
@@ -193,7 +195,7 @@ __device__ __forceinline__ void pack_part(const DevTables &T, const SizeCtx &C, 
     const PartBase pb = resolve_base<Wide>(T, C, base);
     if (!fam) {
         // Sec. 3.1 Eq. (2): word i holds digits i*k .. i*k+k-1, the first at the highest power
-        for (uint32_t i = i0; i < nwords; i += G) dst[i] = horner_digits<Wide>(pb, 0, i * pb.k, pb.k, get);
+        for (uint32_t i = i0; i < nwords; i += G) dst[i] = horner_word<Wide>(pb, 0, i * pb.k, pb.k, n, get);
         return;
     }
     if (pb.D) {
@@ -216,8 +218,8 @@ __device__ __forceinline__ void pack_part(const DevTables &T, const SizeCtx &C, 
         for (uint32_t i = w0; i < w1; i++) {
             if (i > w0) e = adv_entry(T, D, i, q);
             // digits are read in increasing order (the excess-list reader relies on it)
-            const uint64_t acc = horner_digits<Wide>(pb, (uint32_t)rp, q, e->p, get);
-            const uint64_t x = get(q + e->p);
+            const uint64_t acc = horner_word<Wide>(pb, (uint32_t)rp, q, e->p, n, get);
+            const uint64_t x = q + e->p < n ? get(q + e->p) : 0;
             const uint64_t qx = div_magic(x, e->mR);
             dst[i] = acc * e->R + (x - qx * e->R);
             rp = qx;
@@ -402,26 +404,48 @@ __global__ __launch_bounds__(kThreads) void stats_kernel(CompressArgs a) {
         const uint32_t Lb = live ? (uint32_t)min((uint64_t)L, lo.n - (b0 + blk) * L) : 0;
         const V *bv = s_val + (size_t)blk * L;
         uint32_t vmin = 0xFFFFFFFFu, vmax = 0;
-        for (uint32_t j = g; j < Lb; j += G) {
-            const uint32_t v = bv[j];
-            vmin = v < vmin ? v : vmin;
-            vmax = v > vmax ? v : vmax;
+        {
+            uint32_t j = g;
+            for (; j + 3 * G < Lb; j += 4 * G) {  // four LDS reads in flight at a time
+                const uint32_t v0 = bv[j], v1 = bv[j + G], v2 = bv[j + 2 * G], v3 = bv[j + 3 * G];
+                vmin = min(vmin, min(min(v0, v1), min(v2, v3)));
+                vmax = max(vmax, max(max(v0, v1), max(v2, v3)));
+            }
+            for (; j < Lb; j += G) {
+                const uint32_t v = bv[j];
+                vmin = v < vmin ? v : vmin;
+                vmax = v > vmax ? v : vmax;
+            }
         }
         vmin = group_reduce(vmin, G, MinOp(), s_red32);
         vmax = group_reduce(vmax, G, MaxOp(), s_red32);
         const uint64_t B = live ? (uint64_t)vmax - vmin + 1 : 1;
         const uint32_t beta = bitlen64(B - 1);
+        // exhaustive search of a full block: both family sizes of classes 0 and 8 come from one
+        // table entry, loaded here so that the histogram below covers its latency
+        const bool full_tab = variant == PCOMP_SELECT_EXHAUSTIVE && live && B > 1 && Lb == L && s_C.fullW &&
+                              B <= kAtlasDirect;
+        const uint32_t fw = full_tab ? ((const __attribute__((address_space(1))) uint32_t *)s_C.fullW)[B] : 0;
         // bin b = beta - bitlen(d): digits in octave b below the top; n_e(t) = bins 0 .. t-1
         uint32_t ne_t[8];
         ne_t[0] = 0;
         Hist16 hist;
         if (!fixed0) {
             uint64_t lo8 = 0, hi8 = 0;  // 8-bit counters: at most 64 digits per lane
-            for (uint32_t j = g; j < Lb; j += G) {
-                const uint32_t b = beta - bitlen32((uint32_t)bv[j] - vmin);
+            auto count = [&](uint32_t v) {
+                const uint32_t b = beta - bitlen32(v - vmin);
                 lo8 += b < 8 ? (1ull << (8 * b)) : 0;
                 if (learned) hi8 += b >= 8 ? (1ull << (8 * (b < 15 ? b - 8 : 7))) : 0;
+            };
+            uint32_t j = g;
+            for (; j + 3 * G < Lb; j += 4 * G) {  // four LDS reads in flight at a time
+                const uint32_t v0 = bv[j], v1 = bv[j + G], v2 = bv[j + 2 * G], v3 = bv[j + 3 * G];
+                count(v0);
+                count(v1);
+                count(v2);
+                count(v3);
             }
+            for (; j < Lb; j += G) count(bv[j]);
             hist_widen(lo8, hi8, hist);
             hist.w[0] = group_reduce(hist.w[0], G, AddOp(), s_red64);
             hist.w[1] = group_reduce(hist.w[1], G, AddOp(), s_red64);
@@ -509,8 +533,7 @@ __global__ __launch_bounds__(kThreads) void stats_kernel(CompressArgs a) {
         if (live && variant == PCOMP_SELECT_EXHAUSTIVE) {
             // classes 0 and 8: one load of the full-block table, else k(B) once for both families
             uint32_t w0 = 0, w8 = 0;
-            if (B > 1 && Lb == L && s_C.fullW && B <= kAtlasDirect) {
-                const uint32_t fw = ((const __attribute__((address_space(1))) uint32_t *)s_C.fullW)[B];
+            if (full_tab) {
                 w0 = fw & 0xFFFFu;
                 w8 = fw >> 16;
             } else if (B > 1) {
@@ -548,11 +571,15 @@ __global__ __launch_bounds__(kThreads) void stats_kernel(CompressArgs a) {
                 key = (try0 && k0 < key) ? k0 : key;
                 key = (try1 && k1 < key) ? k1 : key;
             }
+        } else if (live && fixed0) {  // one class: the first lane of the group sizes it
+            if (g == 0) {
+                uint32_t nwm;
+                key = ((uint64_t)class_words<(W == 4)>(T, s_C, L, variant, Lb, B, beta, 0, nwm) << 8) |
+                      (uint64_t)variant;
+            }
         } else if (live) {
             for (int c = (int)g; c < 16; c += (int)G) {
-                const bool cand = fixed0 ? (c == variant)
-                                         : (c == 0 || variant == PCOMP_SELECT_EXHAUSTIVE || c == variant ||
-                                            (learned && c == pred));
+                const bool cand = c == 0 || c == variant || (learned && c == pred);
                 const int t = c & 7;
                 if (!cand || t > (int)beta) continue;
                 uint32_t nwm, net = 0;
@@ -816,19 +843,20 @@ __global__ __launch_bounds__(kThreads) void pack_kernel(CompressArgs a) {
         }
         if (live && nw) {
             uint64_t *dst = (uint64_t *)(so + lo.off_payload) + base_off + s_off[blk];
+            // digit readers: pack_part asks only for digits of the part (j < its length)
             if (tcls == 0) {
                 pack_part<(W == 4)>(T, s_C, B, Lb, fam, nw, g, G, dst,
-                          [&](uint32_t j) -> uint64_t { return j < Lb ? (uint64_t)((uint32_t)bv[j] - bmin) : 0; });
+                                    [&](uint32_t j) -> uint64_t { return (uint64_t)((uint32_t)bv[j] - bmin); });
             } else {
+                const uint32_t Th32 = (uint32_t)Th;  // T <= 2^31
                 pack_part<(W == 4)>(T, s_C, Th + 1, Lb, fam, nwm, g, G, dst, [&](uint32_t j) -> uint64_t {
-                    if (j >= Lb) return 0;
-                    const uint64_t d = (uint32_t)bv[j] - bmin;
-                    return d < Th ? d : Th;
+                    const uint32_t d = (uint32_t)bv[j] - bmin;
+                    return (uint64_t)(d < Th32 ? d : Th32);
                 });
                 if (compact) {
                     const V *ex = s_ex + s_exoff[blk];
                     pack_part<(W == 4)>(T, s_C, B - Th, ne, fam, nw - nwm, g, G, dst + nwm,
-                                        [&](uint32_t j) -> uint64_t { return j < ne ? (uint64_t)ex[j] : 0; });
+                                        [&](uint32_t j) -> uint64_t { return (uint64_t)ex[j]; });
                 } else {
                     ExcessReader<V> exr{bv, s_cpre + (tid - g), Lb, ch, G, ne, bmin, (uint32_t)Th, 0, 0, 0};
                     pack_part<(W == 4)>(T, s_C, B - Th, ne, fam, nw - nwm, g, G, dst + nwm,

@@ -46,7 +46,7 @@ __device__ __forceinline__ void set_status(int32_t *st, int32_t code) { atomicMi
 
 // Reads and checks a stream header (in_size bytes are readable); returns false if it is
 // unusable.
-__device__ bool read_layout(const uint8_t *in, uint64_t in_size, Layout &lo, uint64_t &pw, int &fixed) {
+__device__ __forceinline__ bool read_layout(const uint8_t *in, uint64_t in_size, Layout &lo, uint64_t &pw, int &fixed) {
     if (in_size < kHdrBytes) return false;
     const uint64_t *h = (const uint64_t *)in;
     const uint64_t h0 = h[0], h1 = h[1];
@@ -413,7 +413,7 @@ __device__ __forceinline__ void decode_tile(const DevTables &T, const uint8_t *i
             const int t = c & 7;
             bool ok = c < 16 && t <= (int)beta && ne <= Lb && (t != 0 || ne == 0) && (uint64_t)bmin + rng <= vmaxw;
             uint32_t nwm = 0, nw = 0;
-            if (ok) nw = class_words<(W == 4), false>(T, S.C, L, c, Lb, B, beta, ne, nwm);
+            if (ok) nw = class_words<(W == 4)>(T, S.C, L, c, Lb, B, beta, ne, nwm);
             ok = ok && nw <= 2 * Lb;  // each part takes at most one word per value
             if (!ok) nw = nwm = 0;
             S.min[tid] = bmin;

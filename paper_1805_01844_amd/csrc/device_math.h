@@ -53,7 +53,7 @@ __device__ __forceinline__ uint64_t udiv64_48(uint64_t X, uint64_t R, uint64_t &
 // Magic numbers for a divisor d in [1, 2^32], computed on the device: m - 1 =
 // floor((2^l - d) 2^64 / d) by two 64-bit long-division steps on 32-bit limbs
 // (2^l - d < d <= 2^32, so every partial dividend fits 64 bits).
-__device__ inline Magic magic_dev(uint64_t d) {
+__device__ __forceinline__ Magic magic_dev(uint64_t d) {
     Magic mg;
     if (d <= 1) {
         mg.m = 1;
@@ -101,7 +101,7 @@ __device__ __forceinline__ int atlas_index(uint64_t B) {
 }
 
 // Digits per word k(B) = max{k : B^k <= 2^64} (Sec. 3.1, Eq. (1), exact reading). B >= 2.
-__device__ inline uint32_t k_of(const DevTables &T, uint64_t B) {
+__device__ __forceinline__ uint32_t k_of(const DevTables &T, uint64_t B) {
     int ai = atlas_index(B);
     if (ai >= 0) return T.desc[ai].k;
     uint32_t lo = 1, hi = 64;
@@ -123,7 +123,7 @@ struct SlowBase {
 
 // floor(2^64 / B^p) for p = 1 .. k by a chain of quotients (floor(floor(x / a) / b) =
 // floor(x / (a b))); floor(2^64 / B) < 2^48 for these bases.
-__device__ inline SlowBase slow_base(const DevTables &T, uint64_t B) {
+__device__ __forceinline__ SlowBase slow_base(const DevTables &T, uint64_t B) {
     SlowBase sb;
     sb.B = B;
     sb.k = k_of(T, B);  // 2 or 3
@@ -235,7 +235,7 @@ __device__ __forceinline__ const AtlasEntry *adv_entry(const DevTables &T, const
 }
 
 // Words of one family (0 basic Sec. 3.1, 1 advanced Sec. 3.2) for n digits of `base`.
-__device__ inline uint32_t family_words(const DevTables &T, int fam, uint32_t n, uint64_t base) {
+__device__ __forceinline__ uint32_t family_words(const DevTables &T, int fam, uint32_t n, uint64_t base) {
     if (n == 0 || base <= 1) return 0;
     if (!fam) {
         uint32_t k = k_of(T, base);

@@ -190,25 +190,55 @@ struct AddOp {
 };
 
 // ---------------------------------------------------------------------------------------
-// Word counts with per-workgroup caches in LDS: the largest base for k digits per word,
-// and, for the main part of threshold classes (base 2^j + 1), k and the advanced word
-// count of a full block.
+// Word counts with per-workgroup caches in LDS: k(B) by octave, and, for the main part of
+// threshold classes (base 2^j + 1), k and the word counts of a full block.
 // ---------------------------------------------------------------------------------------
+
+// k(B) = max{k : B^k <= 2^64} (Sec. 3.1 Eq. (1), exact reading) for 2 <= B <= 2^32, from small
+// tables: k8[B] for B <= 256; above, B lies in the octave e = bitlen(B - 1) >= 9, where k takes
+// one of two values, ktop[e] = k(2^(e-1) + 1) or one less (64 / (e - 1) - 64 / e < 1 for
+// e >= 9), the larger iff B - 1 <= km1[ktop[e]] = kmax(ktop[e]) - 1 (kmax(k), the largest base
+// with k digits per word, is at most 2^32 for k >= 2).
+__host__ __device__ __forceinline__ uint32_t k_octave(const uint8_t *k8, const uint8_t *ktop, const uint32_t *km1,
+                                                      uint64_t B) {
+    if (B <= 256) return k8[B];
+    const uint32_t bm1 = (uint32_t)(B - 1);
+    const uint32_t e = 32 - (uint32_t)__builtin_clz(bm1);
+    const uint32_t kc = ktop[e];
+    return kc - (bm1 > km1[kc] ? 1u : 0u);
+}
+
+// Entries of those tables, from k(B) for B <= 2^16 + 1 (ktab) and the bounds kmax[k].
+__host__ __device__ __forceinline__ uint32_t ktop_entry(const uint8_t *ktab, const uint64_t *kmax, uint32_t e) {
+    if (e < 9) return 0;  // not used: B <= 256 reads k8
+    const uint64_t B = (1ull << (e - 1)) + 1;
+    if (B <= kAtlasDirect) return ktab[B];
+    uint32_t k = 64 / (e - 1);  // at least k(B); at most two steps down
+    while (B > kmax[k]) k--;
+    return k;
+}
+__host__ __device__ __forceinline__ uint32_t km1_entry(const uint64_t *kmax, uint32_t k) {
+    return k >= 2 ? (uint32_t)((kmax[k] < (1ull << 32) ? kmax[k] : (1ull << 32)) - 1) : 0xFFFFFFFFu;
+}
+
 struct SizeCtx {
-    uint64_t kmax[65];
+    uint8_t k8[260];  // k(B) for B <= 256 (0 for B < 2)
+    uint8_t ktop[36];
+    uint32_t km1[8];  // k <= 7 above B = 256
     uint32_t p1_k[32];
     uint32_t p1_adv[32];
     uint32_t p1_basic[32];  // basic words of a full block of base 2^j + 1
     // per base B <= 2^16 + 1: words of a full block, basic (bits 0-15) and advanced (16-31), or nullptr
     const uint32_t *fullW;
-    const uint8_t *ktab;   // k(B) for every base <= 2^16 + 1
 };
 
-__device__ inline void fill_size_ctx(const DevTables &T, uint32_t L, SizeCtx &C, const uint32_t *fullW = nullptr) {
+__device__ __forceinline__ void fill_size_ctx(const DevTables &T, uint32_t L, SizeCtx &C, const uint32_t *fullW = nullptr) {
     const uint32_t t = threadIdx.x;
     if (t == 200) C.fullW = fullW;
-    if (t == 201) C.ktab = T.ktab;
-    if (t < 65) C.kmax[t] = T.kmax[t];
+    if (t < 256) C.k8[t] = T.ktab[t];
+    if (t == 0) C.k8[256] = T.ktab[256];
+    if (t >= 160 && t < 160 + 33) C.ktop[t - 160] = (uint8_t)ktop_entry(T.ktab, T.kmax, t - 160);
+    if (t >= 224 && t < 232) C.km1[t - 224] = km1_entry(T.kmax, t - 224);
     if (t >= 96 && t < 128) {
         const uint32_t j = t - 96;
         const BaseDesc &D = T.desc[atlas_index((1ull << j) + 1)];
@@ -218,34 +248,16 @@ __device__ inline void fill_size_ctx(const DevTables &T, uint32_t L, SizeCtx &C,
     }
 }
 
-// k(B) = max{k : B^k <= 2^64} for B >= 2 (Sec. 3.1 Eq. (1), exact reading). kTab: bases up to
-// 2^16 + 1 from the per-device table in global memory (one load); otherwise, and for larger
-// bases, a float estimate corrected against the exact bounds in LDS (no global load: the
-// decoder, whose tiles wait on every load, takes this way).
-template <bool kTab = true>
-__device__ __forceinline__ uint32_t k_fast(const SizeCtx &C, uint64_t B) {
-    if (kTab && B <= kAtlasDirect) return ((const __attribute__((address_space(1))) uint8_t *)C.ktab)[B];  // global, not flat
-    uint32_t k = (uint32_t)(64.0f * __builtin_amdgcn_rcpf(__log2f((float)B)));  // corrected below
-    k = k < 1 ? 1 : (k > 63 ? 63 : k);
-    const uint64_t cur = C.kmax[k], up = C.kmax[k + 1];  // both bounds fetched together
-    if (B <= up) {
-        k++;
-        while (k < 64 && B <= C.kmax[k + 1]) k++;
-    } else if (B > cur) {
-        k--;
-        while (B > C.kmax[k]) k--;
-    }
-    return k;
-}
+__device__ __forceinline__ uint32_t k_fast(const SizeCtx &C, uint64_t B) { return k_octave(C.k8, C.ktop, C.km1, B); }
 
 // Words of family fam (0 basic Sec. 3.1, 1 advanced Sec. 3.2) for n digits of `base`;
 // `full` is the block length L (a block of n == L values can use the cache). Wide: the data
 // are u32, so a base can lie outside the tables (u8 and u16 bases never do).
-template <bool Wide, bool kTab = true>
-__device__ inline uint32_t fam_words(const DevTables &T, const SizeCtx &C, int fam, uint32_t n, uint64_t base,
+template <bool Wide>
+__device__ __forceinline__ uint32_t fam_words(const DevTables &T, const SizeCtx &C, int fam, uint32_t n, uint64_t base,
                                      uint32_t full) {
     if (n == 0 || base <= 1) return 0;
-    const uint32_t k = k_fast<kTab>(C, base);
+    const uint32_t k = k_fast(C, base);
     if (!fam) return udiv_small(n + k - 1, k);
     if (n <= k) return 1;
     if (n == full && C.fullW && base <= kAtlasDirect)
@@ -260,12 +272,12 @@ __device__ inline uint32_t fam_words(const DevTables &T, const SizeCtx &C, int f
 
 // Words of the main part (digits min(d, T) in base T + 1, T = 2^(beta - t)) of a threshold
 // class, t >= 1: a lower bound of the class's words.
-template <bool Wide, bool kTab = true>
+template <bool Wide>
 __device__ __forceinline__ uint32_t main_words(const DevTables &T, const SizeCtx &C, uint32_t L, int fam, int t,
                                                uint32_t Lb, uint32_t beta) {
     const uint32_t j = beta - t;
     if (!fam) return Lb == L ? C.p1_basic[j] : udiv_small(Lb + C.p1_k[j] - 1, C.p1_k[j]);
-    return (Lb == L) ? C.p1_adv[j] : fam_words<Wide, kTab>(T, C, 1, Lb, (1ull << j) + 1, L);
+    return (Lb == L) ? C.p1_adv[j] : fam_words<Wide>(T, C, 1, Lb, (1ull << j) + 1, L);
 }
 
 // Advanced words of n digits of `base` once its k is known: one word for n <= k, else the
@@ -282,12 +294,12 @@ __device__ __forceinline__ uint32_t adv_words_k(const DevTables &T, const SizeCt
 
 // Words of class c = 8 family + t for a block of Lb digits of base B (beta = bitlen(B-1));
 // ne_t = digits >= T = 2^(beta - t). nw_main receives the main-part words.
-template <bool Wide, bool kTab = true>
-__device__ inline uint32_t class_words(const DevTables &T, const SizeCtx &C, uint32_t L, int c, uint32_t Lb,
+template <bool Wide>
+__device__ __forceinline__ uint32_t class_words(const DevTables &T, const SizeCtx &C, uint32_t L, int c, uint32_t Lb,
                                        uint64_t B, uint32_t beta, uint32_t ne_t, uint32_t &nw_main) {
     const int fam = c >> 3, t = c & 7;
     if (t == 0) {
-        nw_main = fam_words<Wide, kTab>(T, C, fam, Lb, B, L);
+        nw_main = fam_words<Wide>(T, C, fam, Lb, B, L);
         return nw_main;
     }
     const uint32_t j = beta - t;
@@ -295,8 +307,8 @@ __device__ inline uint32_t class_words(const DevTables &T, const SizeCtx &C, uin
     if (!fam)
         nw_main = udiv_small(Lb + C.p1_k[j] - 1, C.p1_k[j]);
     else
-        nw_main = (Lb == L) ? C.p1_adv[j] : fam_words<Wide, kTab>(T, C, 1, Lb, Th + 1, L);
-    return nw_main + fam_words<Wide, kTab>(T, C, fam, ne_t, B - Th, L);
+        nw_main = (Lb == L) ? C.p1_adv[j] : fam_words<Wide>(T, C, 1, Lb, Th + 1, L);
+    return nw_main + fam_words<Wide>(T, C, fam, ne_t, B - Th, L);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -435,12 +447,12 @@ __host__ __device__ __forceinline__ double pow_exact(double B, uint32_t e) {
 }
 
 // The decoder's constants of a basic-family part, from the base alone (no table load): k(B)
-// from the bounds in LDS, h2, B^h2 by squaring (every power used is at most 2^32, exact in
+// from the octave tables in LDS, h2, B^h2 by squaring (every power used is at most 2^32, exact in
 // binary64), and the correctly rounded reciprocals of IEEE division.
 __device__ __forceinline__ PartBase basic_base(const SizeCtx &C, uint64_t base) {
     PartBase pb;
     pb.base = base;
-    pb.k = k_fast<false>(C, base);
+    pb.k = k_fast(C, base);
     pb.ch.h = 0;
     pb.ch.P = 0;
     pb.ch.h2 = pb.k / 2 > 1 ? pb.k / 2 : 1;
@@ -491,13 +503,42 @@ __device__ __forceinline__ uint64_t horner_digits(const PartBase &pb, uint32_t l
     const uint32_t total = cnt + 1;
     uint32_t first = total - h * udiv_small(total, h);
     if (first == 0) first = h;
-    uint32_t s = lead, j = j0;
-    for (uint32_t m = 1; m < first; m++) s = __umul24(s, B) + (uint32_t)get(j++);
-    uint64_t acc = s;
-    for (uint32_t c = first; c < total; c += h) {
-        s = 0;
-        for (uint32_t m = 0; m < h; m++) s = __umul24(s, B) + (uint32_t)get(j++);
-        acc = acc * pb.ch.P + s;
+    uint32_t j = j0;
+    // m digits into the 24-bit chunk s, four reads in flight at a time (in increasing order)
+    auto chunk = [&](uint32_t s, uint32_t m) -> uint32_t {
+        for (; m >= 4; m -= 4) {
+            const uint32_t d0 = (uint32_t)get(j), d1 = (uint32_t)get(j + 1), d2 = (uint32_t)get(j + 2),
+                           d3 = (uint32_t)get(j + 3);
+            j += 4;
+            s = __umul24(__umul24(__umul24(__umul24(s, B) + d0, B) + d1, B) + d2, B) + d3;
+        }
+        for (; m > 0; m--) s = __umul24(s, B) + (uint32_t)get(j++);
+        return s;
+    };
+    uint64_t acc = chunk(lead, first - 1);
+    for (uint32_t c = first; c < total; c += h) acc = acc * pb.ch.P + chunk(0, h);
+    return acc;
+}
+
+// A word of cnt digits starting at j0, of which only those below n exist (the last word of a
+// part ends with absent digits, which are 0): Horner over the existing ones, then times
+// B^(absent) by squaring (every power used is at most B^(cnt-1) < 2^64). get is asked only for
+// existing digits.
+template <bool Wide, typename Get>
+__device__ __forceinline__ uint64_t horner_word(const PartBase &pb, uint32_t lead, uint32_t j0, uint32_t cnt,
+                                                uint32_t n, Get get) {
+    const uint32_t real = j0 < n ? (cnt < n - j0 ? cnt : n - j0) : 0;
+    uint64_t acc = horner_digits<Wide>(pb, lead, j0, real, get);
+    uint32_t pad = cnt - real;
+    if (pad) {
+        uint64_t p = 1, b = pb.base;
+        for (;;) {
+            if (pad & 1) p *= b;
+            pad >>= 1;
+            if (!pad) break;
+            b *= b;
+        }
+        acc *= p;
     }
     return acc;
 }

@@ -1,5 +1,5 @@
 // Host check of the binary64 digit arithmetic of the HIP decoder (split_word, digit_off in
-// kernels_common.h), against exact integer division. Built with hipcc as host code and run on
+// kernels_common.h), against exact integer division, and of k(B) from the octave tables. Built with hipcc as host code and run on
 // the CPU by tests/test_host_split.py; prints "ok <cases>" or the first mismatch.
 #include <stdint.h>
 #include <stdio.h>
@@ -66,8 +66,50 @@ static int check(uint64_t B, uint64_t X, int full) {
     return 0;
 }
 
+// k(B) from the decoder's and packer's octave tables (k_octave, built as fill_size_ctx builds
+// them, from k(B) for small bases and the bounds kmax[k]) against the exact definition
+static int check_k_tables() {
+    static uint8_t ktab[65538];
+    for (uint64_t B = 0; B <= 65537; B++) ktab[B] = B < 2 ? 0 : (uint8_t)k_of(B);
+    uint64_t kmax[65];
+    kmax[0] = 0;
+    kmax[1] = UINT64_MAX;
+    for (uint32_t k = 2; k <= 64; k++) {  // largest B with B^k <= 2^64, by bisection
+        uint64_t lo = 1, hi = 1ull << 32;
+        while (lo < hi) {
+            const uint64_t mid = lo + (hi - lo + 1) / 2;
+            if (k_of(mid) >= k) lo = mid; else hi = mid - 1;
+        }
+        kmax[k] = lo;
+    }
+    uint8_t k8[260], ktop[36];
+    uint32_t km1[8];
+    for (uint32_t t = 0; t <= 256; t++) k8[t] = ktab[t];
+    for (uint32_t e = 0; e < 33; e++) ktop[e] = (uint8_t)pcomp::ktop_entry(ktab, kmax, e);
+    for (uint32_t k = 0; k < 8; k++) km1[k] = pcomp::km1_entry(kmax, k);
+    auto one = [&](uint64_t B) {
+        cases++;
+        if (pcomp::k_octave(k8, ktop, km1, B) != k_of(B)) {
+            printf("k mismatch B=%llu\n", (unsigned long long)B);
+            return 1;
+        }
+        return 0;
+    };
+    for (uint64_t B = 2; B <= (1u << 20); B++)
+        if (one(B)) return 1;
+    for (uint32_t k = 2; k < 8; k++)
+        for (int d = -2; d <= 2; d++)
+            if (kmax[k] + d >= 2 && kmax[k] + d <= (1ull << 32) && one(kmax[k] + d)) return 1;
+    for (uint32_t e = 9; e <= 32; e++)
+        for (int d = -2; d <= 2; d++)
+            if ((1ull << e) + d <= (1ull << 32) && one((1ull << e) + d)) return 1;
+    for (int r = 0; r < 2000000; r++)
+        if (one(2 + next64() % ((1ull << 32) - 1))) return 1;
+    return 0;
+}
+
 int main() {
-    int bad = 0;
+    int bad = check_k_tables();
     for (uint64_t B = 2; B <= 65537 && !bad; B++) {
         u128 Bk = 1;
         for (uint32_t i = 0; i < k_of(B); i++) Bk *= B;
