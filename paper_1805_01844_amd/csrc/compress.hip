@@ -353,10 +353,18 @@ __device__ __forceinline__ void copy_size_ctx(const SizeCtx *g, SizeCtx &s) {
 }
 
 // ---- launch 2: block statistics, class choice, block arrays, tile totals ----------------
-template <int W, bool kPersist, bool kLearned>
+// kPair (tiles of 128 blocks, not persistent): a workgroup takes two consecutive tiles, staged
+// side by side in dynamic LDS, and every lane one block (lanes 0-127 the first tile, 128-255
+// the second), so no block's work is split between lanes.
+constexpr uint32_t kPairBlocks = kThreads / 2;
+// 16-byte chunks that a staged tile of tile_bytes may cover (its first value need not be aligned)
+__host__ __device__ inline uint32_t pair_region(uint32_t tile_bytes) { return (tile_bytes + 15) / 16 + 1; }
+template <int W, bool kPersist, bool kLearned, bool kPair = false>
 __global__ __launch_bounds__(kThreads) void stats_kernel(CompressArgs a) {
     typedef typename Elem<W>::T V;
-    __shared__ uint4 s_raw[kTileBytes / 16 + 1];
+    __shared__ uint4 s_one[kPair ? 1 : kTileBytes / 16 + 1];
+    extern __shared__ uint4 s_pair[];  // kPair: two regions of pair_region(tile bytes) chunks
+    uint4 *const s_raw = kPair ? s_pair : s_one;
     __shared__ uint32_t s_nw[kMaxTileBlocks];
     __shared__ uint8_t s_pred[kMaxTileBlocks];
     __shared__ uint64_t s_red64[kThreads / 64];
@@ -374,18 +382,50 @@ __global__ __launch_bounds__(kThreads) void stats_kernel(CompressArgs a) {
     // serialisation (read before the first tile's barrier)
     if (kLearned)
         for (uint32_t i = tid; i < (uint32_t)kMlpParams; i += kThreads) s_model[i] = c_model[i];
-    for (uint64_t gt = a.tile_lo + blockIdx.x; gt < a.tile_hi; gt = kPersist ? gt + gridDim.x : a.tile_hi) {
+    const uint32_t span = kPair ? 2 : 1;
+    for (uint64_t gt0 = a.tile_lo + span * blockIdx.x; gt0 < a.tile_hi; gt0 = kPersist ? gt0 + gridDim.x : a.tile_hi) {
+        const uint32_t half = kPair ? tid / kPairBlocks : 0;
+        const uint64_t gt = gt0 + half;
+        const bool valid = gt < a.tile_hi;
         uint32_t sj;
-        const SegDesc sd = seg_of(a, gt, sj);
+        const SegDesc sd = seg_of(a, valid ? gt : gt0, sj);
         const Layout &lo = sd.lo;
         const uint32_t L = lo.L, tb = lo.tile_blocks;
         const uint64_t b0 = (gt - sd.tile0) * tb;
-        const uint32_t nbt = (uint32_t)min((uint64_t)tb, lo.n_blocks - b0);
+        const uint32_t nbt = valid ? (uint32_t)min((uint64_t)tb, lo.n_blocks - b0) : 0;
         const uint64_t v0 = b0 * L;
-        const uint32_t nvt = (uint32_t)min((uint64_t)nbt * L, lo.n - v0);
-        // one workgroup per tile: all of its loads at once (persistent grids keep fewer registers)
+        const uint32_t nvt = valid ? (uint32_t)min((uint64_t)nbt * L, lo.n - v0) : 0;
+        // one workgroup per tile (or pair): all of its loads at once (persistent grids keep fewer
+        // registers)
         const V *s_val;
-        if (sd.rows) {
+        if (kPair) {
+            // the whole workgroup stages both tiles (the second may lie in another segment)
+            const uint32_t region = pair_region(tb * L * W);
+            const V *first[2] = {nullptr, nullptr};
+            TileRef tr[2];
+            Staged stg[2];
+            bool have[2];
+#pragma unroll
+            for (uint32_t h = 0; h < 2; h++) {
+                const uint64_t gh = gt0 + h;
+                have[h] = gh < a.tile_hi;
+                uint32_t jh;
+                const SegDesc sh = seg_of(a, have[h] ? gh : gt0, jh);
+                const uint64_t vh = (gh - sh.tile0) * sh.lo.tile_blocks * sh.lo.L;
+                const uint32_t nh = have[h] ? (uint32_t)min((uint64_t)sh.lo.tile_blocks * sh.lo.L, sh.lo.n - vh) : 0;
+                if (sh.rows) {
+                    first[h] = have[h] ? stage_tile_tm<W>(sh, vh, nh, s_raw + h * region) : nullptr;
+                    have[h] = false;  // staged already
+                } else {
+                    tr[h] = tile_ref<W>(sh, vh, nh);
+                    if (have[h]) tile_fetch(tr[h], stg[h]);
+                }
+            }
+#pragma unroll
+            for (uint32_t h = 0; h < 2; h++)
+                if (have[h]) first[h] = tile_commit<W>(tr[h], stg[h], s_raw + h * region);
+            s_val = half ? first[1] : first[0];
+        } else if (sd.rows) {
             s_val = stage_tile_tm<W>(sd, v0, nvt, s_raw);
         } else if (kPersist) {
             s_val = stage_tile<W>(sd.data, v0, nvt, s_raw);
@@ -398,8 +438,8 @@ __global__ __launch_bounds__(kThreads) void stats_kernel(CompressArgs a) {
         __syncthreads();
 
         // per block: min / max (B = v_max - v_min + 1) and excess counts
-        const uint32_t G = kThreads / tb;
-        const uint32_t blk = tid / G, g = tid % G;
+        const uint32_t G = kPair ? 1 : kThreads / tb;
+        const uint32_t blk = kPair ? tid % kPairBlocks : tid / G, g = kPair ? 0 : tid % G;
         const bool live = blk < nbt;
         const uint32_t Lb = live ? (uint32_t)min((uint64_t)L, lo.n - (b0 + blk) * L) : 0;
         const V *bv = s_val + (size_t)blk * L;
@@ -541,36 +581,38 @@ __global__ __launch_bounds__(kThreads) void stats_kernel(CompressArgs a) {
                 w0 = udiv_small(Lb + kb - 1, kb);
                 w8 = adv_words_k<(W == 4)>(T, s_C, Lb, B, kb, L);
             }
-            key = (uint64_t)w0 << 8;
-            if (beta >= 1) {
-                const uint64_t k8 = ((uint64_t)w8 << 8) | 8;
-                key = k8 < key ? k8 : key;
-            }
-            // lanes split the thresholds t; each sizes both families of its t, which share the
-            // excess base B - T and its digits per word
-            for (int t = 1 + (int)g; t < 8; t += (int)G) {
-                if (t > (int)beta) break;
-                uint32_t net = 0;
+            // keys (words << 8 | id) in 32 bits: a block of at most 2^16 values has fewer than 2^24 words
+            uint32_t k32 = w0 << 8;
+            if (beta >= 1) k32 = min(k32, (w8 << 8) | 8u);
+            // lanes split the thresholds t (unrolled, so that n_e(t) is read without an index); each
+            // sizes both families of its t, which share the excess base B - T and its digits per
+            // word. Every t <= beta has a non-empty excess list (the maximum digit B - 1 >= T), so
+            // a class whose main part plus one word cannot beat the key is skipped, and so is the
+            // advanced one whose main part plus the least possible excess words cannot.
 #pragma unroll
-                for (int tt = 1; tt < 8; tt++) net = (t == tt) ? ne_t[tt] : net;  // no dynamic register index
+            for (int t = 1; t < 8; t++) {
+                if ((uint32_t)(t - 1) % G != g || t > (int)beta) continue;
+                const uint32_t net = ne_t[t];
                 const uint32_t m0 = main_words<(W == 4)>(T, s_C, L, 0, t, Lb, beta);
                 const uint32_t m1 = main_words<(W == 4)>(T, s_C, L, 1, t, Lb, beta);
-                const uint32_t one = net ? 1 : 0;
-                const bool try0 = ((((uint64_t)(m0 + one)) << 8) | (uint64_t)t) < key;
-                const bool try1 = ((((uint64_t)(m1 + one)) << 8) | (uint64_t)(8 + t)) < key;
+                const bool try0 = (((m0 + 1) << 8) | (uint32_t)t) < k32;
+                bool try1 = (((m1 + 1) << 8) | (uint32_t)(8 + t)) < k32;
                 if (!try0 && !try1) continue;
                 const uint64_t Be = B - (1ull << (beta - t));
                 uint32_t e0 = 0, e1 = 0;
-                if (net && Be > 1) {
+                if (Be > 1) {
                     const uint32_t ke = k_fast(s_C, Be);
                     e0 = udiv_small(net + ke - 1, ke);
-                    e1 = adv_words_k<(W == 4)>(T, s_C, net, Be, ke, L);
+                    if (try1) {
+                        const uint32_t lo1 = net <= ke ? 1 : udiv_small(net + 1 + ke, ke + 1);  // every word takes <= k + 1
+                        try1 = (((m1 + lo1) << 8) | (uint32_t)(8 + t)) < k32;
+                        if (try1) e1 = adv_words_k<(W == 4)>(T, s_C, net, Be, ke, L);
+                    }
                 }
-                const uint64_t k0 = ((uint64_t)(m0 + e0) << 8) | (uint64_t)t;
-                const uint64_t k1 = ((uint64_t)(m1 + e1) << 8) | (uint64_t)(8 + t);
-                key = (try0 && k0 < key) ? k0 : key;
-                key = (try1 && k1 < key) ? k1 : key;
+                if (try0) k32 = min(k32, ((m0 + e0) << 8) | (uint32_t)t);
+                if (try1) k32 = min(k32, ((m1 + e1) << 8) | (uint32_t)(8 + t));
             }
+            key = k32;
         } else if (live && fixed0) {  // one class: the first lane of the group sizes it
             if (g == 0) {
                 uint32_t nwm;
@@ -604,17 +646,23 @@ __global__ __launch_bounds__(kThreads) void stats_kernel(CompressArgs a) {
 #pragma unroll
         for (int tt = 1; tt < 8; tt++) ne = (tcls == tt) ? ne_t[tt] : ne;
         if (live && g == 0) {
-            s_nw[blk] = nw;
+            if (!kPair) s_nw[blk] = nw;
             const uint64_t r = (gt - a.tile_lo) * tb + blk;
             const Recs<W> rc(a.rec, a.rec_n);
             ((V *)rc.min)[r] = (V)vmin;
             ((V *)rc.rng)[r] = (V)(B - 1);
             rc.meta[r] = (uint32_t)cls | (nw << 4) | (ne << 16);
         }
-        __syncthreads();
-        uint32_t total;
-        wg_excl_scan(tid < nbt ? s_nw[tid] : 0, s_red32, &total);
-        if (tid == 0) a.tile_words[gt] = total;
+        if (kPair) {  // each half's tile total
+            const uint32_t total = group_reduce(live ? nw : 0u, kPairBlocks, AddOp(), s_red32);
+            if (valid && blk == 0) a.tile_words[gt] = total;
+            __syncthreads();  // LDS is reused by the next pair
+        } else {
+            __syncthreads();
+            uint32_t total;
+            wg_excl_scan(tid < nbt ? s_nw[tid] : 0, s_red32, &total);
+            if (tid == 0) a.tile_words[gt] = total;
+        }
     }
 }
 
@@ -928,9 +976,12 @@ uint64_t compress_ws_bytes(uint64_t n_tiles, uint32_t n_segs, const uint64_t *ti
 // One per-tile launch (stats or pack) of width W; a persistent grid walks the tiles with a
 // stride, otherwise every workgroup takes one tile (the kernel then holds fewer registers).
 template <int W>
-void launch_tiles(bool stats, bool persist, uint32_t grid, size_t dyn, const CompressArgs &b, hipStream_t st) {
+void launch_tiles(bool stats, bool persist, uint32_t grid, size_t dyn, const CompressArgs &b, hipStream_t st,
+                  uint32_t tile_blocks = 0, uint32_t tile_bytes = 0) {
     const bool learned = b.variant == PCOMP_SELECT_LEARNED;
-    if (stats && learned) {
+    if (stats && !learned && !persist && tile_blocks == kPairBlocks) {  // pairs of tiles, one lane per block
+        stats_kernel<W, false, false, true><<<(grid + 1) / 2, kThreads, 2 * 16 * pair_region(tile_bytes), st>>>(b);
+    } else if (stats && learned) {
         if (persist)
             stats_kernel<W, true, true><<<grid, kThreads, 0, st>>>(b);
         else
@@ -1002,12 +1053,13 @@ int launch_compress_table(const SegDesc *segs, const uint32_t *tile_seg, const u
         b.rec_n = wl.rec_n[g];
         const bool persist = grid && grid < ntg;
         const uint32_t gg = (uint32_t)(persist ? grid : ntg);
+        const uint32_t w = 1u << g, tbg = tile_blocks_of(L[g], w);
         if (g == 0)
-            launch_tiles<1>(true, persist, gg, 0, b, st);
+            launch_tiles<1>(true, persist, gg, 0, b, st, tbg, tbg * L[g] * w);
         else if (g == 1)
-            launch_tiles<2>(true, persist, gg, 0, b, st);
+            launch_tiles<2>(true, persist, gg, 0, b, st, tbg, tbg * L[g] * w);
         else
-            launch_tiles<4>(true, persist, gg, 0, b, st);
+            launch_tiles<4>(true, persist, gg, 0, b, st, tbg, tbg * L[g] * w);
     }
     const uint32_t runs = (uint32_t)((n_tiles + kScanTiles - 1) / kScanTiles);
     if (runs > 0) {
