@@ -515,7 +515,7 @@ def main():
     # (plus a 4-byte status reset), timed live above on the stream it is launched on; its
     # algorithmic bytes are the stream it reads plus the values it writes. Compression is a
     # pipeline of launches (statistics, scan, placement, packing) and is reported as a whole.
-    kern = "decompress_kernel<2, false>"
+    kern = "decompress_kernel<2, false, false>"
     alg = stream_len + nbytes
     roof = _roofline(alg, td)
     roof.update({"kernel": kern, "traffic": traffic_from_profiles(kern), "launch_ms": round(td * 1e3, 4),

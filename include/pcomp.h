@@ -16,8 +16,9 @@
  *     clipped to T in the main digits and their excess is packed separately
  *     (threshold/excess classes t = 1..7, a value split in the spirit of the
  *     r / r' split of Sec. 3.2);
- *   - decompression is the inverse polynomial division (Sec. 3.1), done with
- *     multiply-high magic-number division.
+ *   - decompression is the inverse polynomial division (Sec. 3.1): digits come
+ *     out as exact binary64 quotients of a word's two halves, and the advanced
+ *     series' divisions by R_i use multiply-high magic numbers.
  *
  * Conventions for every entry point:
  *   - d_* pointers are DEVICE pointers (HBM of the current HIP device), h_*
