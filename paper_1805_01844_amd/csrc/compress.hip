@@ -359,7 +359,9 @@ __device__ __forceinline__ void copy_size_ctx(const SizeCtx *g, SizeCtx &s) {
 constexpr uint32_t kPairBlocks = kThreads / 2;
 // 16-byte chunks that a staged tile of tile_bytes may cover (its first value need not be aligned)
 __host__ __device__ inline uint32_t pair_region(uint32_t tile_bytes) { return (tile_bytes + 15) / 16 + 1; }
-template <int W, bool kPersist, bool kLearned, bool kPair = false>
+// kLearn: 0 = no learned selector; 1 = learned, the lanes of a block share its network (tiles of
+// at most kMaxTileBlocks / 4 blocks); 2 = learned, one thread scores a block (larger tiles).
+template <int W, bool kPersist, int kLearn, bool kPair = false>
 __global__ __launch_bounds__(kThreads) void stats_kernel(CompressArgs a) {
     typedef typename Elem<W>::T V;
     __shared__ uint4 s_one[kPair ? 1 : kTileBytes / 16 + 1];
@@ -370,18 +372,30 @@ __global__ __launch_bounds__(kThreads) void stats_kernel(CompressArgs a) {
     __shared__ uint64_t s_red64[kThreads / 64];
     __shared__ uint32_t s_red32[kThreads / 64];
     __shared__ SizeCtx s_C;
-    __shared__ float s_model[kLearned ? kMlpParams : 1];  // the selector's parameters, per workgroup
+    // the selector's parameters, per workgroup: W1, b1 and b2 (at kMlpW2) in s_model; W2 in s_w2s,
+    // row k holding W2[k][j] at column j ^ 4k, so that the 16 lanes that score the 16 classes read
+    // their rows' quads j .. j + 3 from 16 different bank groups
+    __shared__ float s_model[kLearn ? kMlpW2 + kMlpOut : 1];
+    __shared__ __align__(16) float s_w2s[kLearn ? kMlpOut * kMlpHid : 4];
+    // the features of the tile's blocks (lane-shared scoring)
+    __shared__ float s_x[kLearn == 1 ? (kMaxTileBlocks / 4) * kMlpIn : 1];
 
     const DevTables &T = a.T;
     const uint32_t tid = threadIdx.x;
     const int variant = a.variant;
     const bool fixed0 = (variant == 0 || variant == 8);
-    const bool learned = kLearned;  // the variant is PCOMP_SELECT_LEARNED
+    const bool learned = kLearn != 0;  // the variant is PCOMP_SELECT_LEARNED
     copy_size_ctx(a.ctx, s_C);
     // lanes read different weights at once: LDS serves those reads without the constant cache's
     // serialisation (read before the first tile's barrier)
-    if (kLearned)
-        for (uint32_t i = tid; i < (uint32_t)kMlpParams; i += kThreads) s_model[i] = c_model[i];
+    if (kLearn) {
+        for (uint32_t i = tid; i < (uint32_t)(kMlpW2 + kMlpOut); i += kThreads)
+            s_model[i] = c_model[i < (uint32_t)kMlpW2 ? i : i + kMlpOut * kMlpHid];
+        for (uint32_t i = tid; i < (uint32_t)(kMlpOut * kMlpHid); i += kThreads) {
+            const uint32_t k = i / kMlpHid, j = (i % kMlpHid) ^ (k << 2);
+            s_w2s[i] = c_model[kMlpW2 + k * kMlpHid + j];
+        }
+    }
     const uint32_t span = kPair ? 2 : 1;
     for (uint64_t gt0 = a.tile_lo + span * blockIdx.x; gt0 < a.tile_hi; gt0 = kPersist ? gt0 + gridDim.x : a.tile_hi) {
         const uint32_t half = kPair ? tid / kPairBlocks : 0;
@@ -442,7 +456,7 @@ __global__ __launch_bounds__(kThreads) void stats_kernel(CompressArgs a) {
         const uint32_t blk = kPair ? tid % kPairBlocks : tid / G, g = kPair ? 0 : tid % G;
         const bool live = blk < nbt;
         const uint32_t Lb = live ? (uint32_t)min((uint64_t)L, lo.n - (b0 + blk) * L) : 0;
-        const V *bv = s_val + (size_t)blk * L;
+        const auto *bv = lds_ptr(s_val + (size_t)blk * L);
         uint32_t vmin = 0xFFFFFFFFu, vmax = 0;
         {
             uint32_t j = g;
@@ -471,22 +485,36 @@ __global__ __launch_bounds__(kThreads) void stats_kernel(CompressArgs a) {
         ne_t[0] = 0;
         Hist16 hist;
         if (!fixed0) {
-            uint64_t lo8 = 0, hi8 = 0;  // 8-bit counters: at most 64 digits per lane
+            // bin b of digit d = v - v_min: b = beta - bitlen(d) = 4-bit counter min(b, 15) of c4,
+            // moved to 8-bit counters of the even and odd bins (ev8, od8) after at most 15
+            // values; at most 64 values per lane, so 8 bits suffice. Bins past 7 matter only to
+            // the learned selector. Below 2^31, bitlen(d) = 31 - clz(2d + 1), and 2d + 1 =
+            // 2v + c1 (mod 2^32) never vanishes; u32 values take clz(d), 32 for d = 0.
+            const uint32_t c1 = 1u - 2u * vmin;
+            uint32_t kofs = 4u * beta - (W == 4 ? 128u : 124u);  // shift = 4 clz + kofs = 4b
+            asm volatile("" : "+v"(kofs));  // kept whole: one multiply-add per value, not two adds
+            uint64_t c4 = 0, ev8 = 0, od8 = 0;
             auto count = [&](uint32_t v) {
-                const uint32_t b = beta - bitlen32(v - vmin);
-                lo8 += b < 8 ? (1ull << (8 * b)) : 0;
-                if (learned) hi8 += b >= 8 ? (1ull << (8 * (b < 15 ? b - 8 : 7))) : 0;
+                const uint32_t z = W == 4 ? (uint32_t)__clz((int)(v - vmin)) : (uint32_t)__builtin_clz(2u * v + c1);
+                c4 += 1ull << min(4u * z + kofs, 60u);
             };
             uint32_t j = g;
-            for (; j + 3 * G < Lb; j += 4 * G) {  // four LDS reads in flight at a time
-                const uint32_t v0 = bv[j], v1 = bv[j + G], v2 = bv[j + 2 * G], v3 = bv[j + 3 * G];
-                count(v0);
-                count(v1);
-                count(v2);
-                count(v3);
+            while (j < Lb) {
+                uint32_t q = 0;
+                for (; q < 3 && j + 3 * G < Lb; q++, j += 4 * G) {  // four LDS reads in flight at a time
+                    const uint32_t v0 = bv[j], v1 = bv[j + G], v2 = bv[j + 2 * G], v3 = bv[j + 3 * G];
+                    count(v0);
+                    count(v1);
+                    count(v2);
+                    count(v3);
+                }
+                if (q < 3)  // fewer than four values left: at most 11 in this round
+                    for (; j < Lb; j += G) count(bv[j]);
+                ev8 += c4 & 0x0F0F0F0F0F0F0F0Full;
+                od8 += (c4 >> 4) & 0x0F0F0F0F0F0F0F0Full;
+                c4 = 0;
             }
-            for (; j < Lb; j += G) count(bv[j]);
-            hist_widen(lo8, hi8, hist);
+            hist_widen_eo(ev8, od8, hist);
             hist.w[0] = group_reduce(hist.w[0], G, AddOp(), s_red64);
             hist.w[1] = group_reduce(hist.w[1], G, AddOp(), s_red64);
             if (learned) {
@@ -500,43 +528,53 @@ __global__ __launch_bounds__(kThreads) void stats_kernel(CompressArgs a) {
             for (int t = 1; t < 8; t++) ne_t[t] = 0;
         }
 
-        // learned selector. With at least 4 lanes per block (tile_blocks <= 64) the block's
-        // lanes share its network: hidden units through LDS (the tile's values are no longer
-        // needed), then the scores; otherwise the features go through LDS and one thread per
-        // block scores it. Both keep every sum's order, so the scores are the same bits.
+        // learned selector. With at least 4 lanes per block (tile_blocks <= 64) the block's lanes
+        // share its features (one division each) and hidden units through LDS, and then every lane
+        // of the workgroup scores one class of one block (16 lanes a block, the tile's values no
+        // longer needed); otherwise the features go through LDS and one thread per block scores it.
+        // Both keep every sum's order, so the scores are the same bits.
         int pred = 0;
-        if (learned && tb <= kMaxTileBlocks / 4) {
+        if (kLearn == 1) {
+            if (live)
+                for (uint32_t f = g; f < (uint32_t)kMlpIn; f += G)
+                    s_x[blk * kMlpIn + f] = block_feature(f, hist.w, Lb, vmin, vmax);
             __syncthreads();
-            float *s_h = (float *)s_raw;  // [tile_blocks][kMlpHid]
+            // hidden unit j of block b at b * kMlpHid + (j ^ 4 (b mod 4)): the four blocks scored
+            // by one wave read their quads from four bank groups
+            float *s_h = (float *)s_raw;
             if (live) {
-                uint32_t H[16];
-#pragma unroll
-                for (int b = 0; b < 16; b++) H[b] = hist_bin(hist, b);
-                float x[kMlpIn];
-                block_features(H, Lb, vmin, vmax, x);
+                const float *xb = s_x + blk * kMlpIn;
                 for (uint32_t j = g; j < (uint32_t)kMlpHid; j += G) {
                     float acc = s_model[kMlpB1 + j];
 #pragma unroll
-                    for (int i = 0; i < kMlpIn; i++) acc = __builtin_fmaf(s_model[kMlpW1 + j * kMlpIn + i], x[i], acc);
-                    s_h[blk * kMlpHid + j] = acc > 0.0f ? acc : 0.0f;
+                    for (int i = 0; i < kMlpIn; i++) acc = __builtin_fmaf(s_model[kMlpW1 + j * kMlpIn + i], xb[i], acc);
+                    s_h[blk * kMlpHid + (j ^ ((blk & 3) << 2))] = acc > 0.0f ? acc : 0.0f;
                 }
             }
             __syncthreads();
-            uint64_t best = 0;  // (order-preserving score bits, 15 - class): the first top score
-            if (live) {
-                for (uint32_t k = g; k < (uint32_t)kMlpOut; k += G) {
-                    float acc = s_model[kMlpB2 + k];
-                    for (int j = 0; j < kMlpHid; j++)
-                        acc = __builtin_fmaf(s_model[kMlpW2 + k * kMlpHid + j], s_h[blk * kMlpHid + j], acc);
-                    uint32_t u = __float_as_uint(acc == 0.0f ? 0.0f : acc);
-                    u = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
-                    const uint64_t key = ((uint64_t)u << 32) | (uint64_t)(15 - k);
-                    best = key > best ? key : best;
+            for (uint32_t q = tid; q < nbt * kMlpOut; q += kThreads) {  // 16-lane groups stay whole
+                const uint32_t sb = q / kMlpOut, k = q % kMlpOut;
+                const float4 *hq = (const float4 *)(s_h + sb * kMlpHid);
+                const float4 *wq = (const float4 *)(s_w2s + k * kMlpHid);
+                float acc = s_model[kMlpW2 + k];  // b2[k]
+#pragma unroll 4
+                for (uint32_t jq = 0; jq < (uint32_t)kMlpHid / 4; jq++) {
+                    const float4 h = hq[jq ^ (sb & 3)], w = wq[jq ^ k];
+                    acc = __builtin_fmaf(w.x, h.x, acc);
+                    acc = __builtin_fmaf(w.y, h.y, acc);
+                    acc = __builtin_fmaf(w.z, h.z, acc);
+                    acc = __builtin_fmaf(w.w, h.w, acc);
                 }
+                uint32_t u = __float_as_uint(acc == 0.0f ? 0.0f : acc);
+                u = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+                // (order-preserving score bits, 15 - class): the largest is the first top score
+                uint64_t best = ((uint64_t)u << 32) | (uint64_t)(15 - k);
+                best = group_reduce(best, kMlpOut, MaxOp(), s_red64);
+                if (k == 0) s_pred[sb] = (uint8_t)(15 - (int)(best & 0xFF));
             }
-            best = group_reduce(best, G, MaxOp(), s_red64);
-            pred = live ? 15 - (int)(best & 0xFF) : 0;
-        } else if (learned) {
+            __syncthreads();
+            pred = live ? s_pred[blk] : 0;
+        } else if (kLearn == 2) {
             __syncthreads();
             uint32_t *s_feat = (uint32_t *)s_raw;  // kFeatWords per block
             if (live && g == 0) {
@@ -558,7 +596,14 @@ __global__ __launch_bounds__(kThreads) void stats_kernel(CompressArgs a) {
                 for (int b = 0; b < 16; b++) H[b] = (f[b >> 1] >> (16 * (b & 1))) & 0xFFFF;
                 float x[kMlpIn], sc[kMlpOut];
                 block_features(H, f[10], f[8], f[9], x);
-                mlp_scores([&](int i) { return s_model[i]; }, x, sc);
+                mlp_scores(
+                    [&](int i) {
+                        if (i < kMlpW2) return s_model[i];
+                        if (i >= kMlpB2) return s_model[i - kMlpOut * kMlpHid];
+                        const int k = (i - kMlpW2) / kMlpHid, j = (i - kMlpW2) % kMlpHid;
+                        return s_w2s[k * kMlpHid + (j ^ (k << 2))];
+                    },
+                    x, sc);
                 s_pred[tid] = (uint8_t)argmax16(sc);
             }
             __syncthreads();
@@ -980,17 +1025,22 @@ void launch_tiles(bool stats, bool persist, uint32_t grid, size_t dyn, const Com
                   uint32_t tile_blocks = 0, uint32_t tile_bytes = 0) {
     const bool learned = b.variant == PCOMP_SELECT_LEARNED;
     if (stats && !learned && !persist && tile_blocks == kPairBlocks) {  // pairs of tiles, one lane per block
-        stats_kernel<W, false, false, true><<<(grid + 1) / 2, kThreads, 2 * 16 * pair_region(tile_bytes), st>>>(b);
+        stats_kernel<W, false, 0, true><<<(grid + 1) / 2, kThreads, 2 * 16 * pair_region(tile_bytes), st>>>(b);
+    } else if (stats && learned && tile_blocks && tile_blocks <= kMaxTileBlocks / 4) {  // all tiles have tile_blocks
+        if (persist)
+            stats_kernel<W, true, 1><<<grid, kThreads, 0, st>>>(b);
+        else
+            stats_kernel<W, false, 1><<<grid, kThreads, 0, st>>>(b);
     } else if (stats && learned) {
         if (persist)
-            stats_kernel<W, true, true><<<grid, kThreads, 0, st>>>(b);
+            stats_kernel<W, true, 2><<<grid, kThreads, 0, st>>>(b);
         else
-            stats_kernel<W, false, true><<<grid, kThreads, 0, st>>>(b);
+            stats_kernel<W, false, 2><<<grid, kThreads, 0, st>>>(b);
     } else if (stats) {
         if (persist)
-            stats_kernel<W, true, false><<<grid, kThreads, 0, st>>>(b);
+            stats_kernel<W, true, 0><<<grid, kThreads, 0, st>>>(b);
         else
-            stats_kernel<W, false, false><<<grid, kThreads, 0, st>>>(b);
+            stats_kernel<W, false, 0><<<grid, kThreads, 0, st>>>(b);
     } else if (persist) {
         pack_kernel<W, true><<<grid, kThreads, dyn, st>>>(b);
     } else {

@@ -177,6 +177,13 @@ struct TmCursor {
     }
 };
 
+// A pointer into LDS, as the compiler sees it: a staged tile chosen among several buffers can
+// lose that address space, and its reads would then take flat addressing.
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(3))) T *lds_ptr(const T *p) {
+    return (const __attribute__((address_space(3))) T *)p;
+}
+
 struct MinOp {
     __device__ uint32_t operator()(uint32_t a, uint32_t b) const { return a < b ? a : b; }
     __device__ uint64_t operator()(uint64_t a, uint64_t b) const { return a < b ? a : b; }
@@ -342,6 +349,20 @@ __device__ __forceinline__ void block_features(const uint32_t *H, uint32_t Lb, u
     x[18] = fl * (1.0f / 4096.0f);
 }
 
+// Feature f alone, the same value as block_features' x[f]; the counts come packed four to a word
+// (bin b in bits 16 (b mod 4) of word b / 4), selected without a dynamic register index.
+__device__ __forceinline__ float block_feature(uint32_t f, const uint64_t *hw, uint32_t Lb, uint64_t vmin,
+                                               uint64_t vmax) {
+    const float fl = (float)Lb;
+    if (f < 16) {
+        const uint32_t q = f >> 2;
+        const uint64_t w = q == 0 ? hw[0] : q == 1 ? hw[1] : q == 2 ? hw[2] : hw[3];
+        return (float)((uint32_t)(w >> (16 * (f & 3))) & 0xFFFFu) / fl;
+    }
+    if (f < 18) return lg_f32((f == 16 ? vmin : vmax) + 1) * 0.03125f;
+    return fl * (1.0f / 4096.0f);
+}
+
 // The 16 scores; P(i) returns parameter i.
 template <typename P>
 __device__ __forceinline__ void mlp_scores(P prm, const float *x, float *s) {
@@ -384,6 +405,15 @@ __device__ __forceinline__ void hist_widen(uint64_t lo8, uint64_t hi8, Hist16 &h
         h.w[1] |= ((lo8 >> (8 * (t + 4))) & 0xFF) << (16 * t);
         h.w[2] |= ((hi8 >> (8 * t)) & 0xFF) << (16 * t);
         h.w[3] |= ((hi8 >> (8 * (t + 4))) & 0xFF) << (16 * t);
+    }
+}
+
+// The same from 8-bit counters of the even bins (ev8, byte i = bin 2i) and the odd bins (od8).
+__device__ __forceinline__ void hist_widen_eo(uint64_t ev8, uint64_t od8, Hist16 &h) {
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        const uint64_t e = (ev8 >> (16 * q)) & 0xFFFF, o = (od8 >> (16 * q)) & 0xFFFF;  // bins 4q .. 4q + 3
+        h.w[q] = (e & 0xFF) | ((o & 0xFF) << 16) | ((e >> 8) << 32) | ((o >> 8) << 48);
     }
 }
 

@@ -72,7 +72,7 @@ def test_no_calls_and_no_stack_objects(resources):
 
 def test_camera_kernels_keep_their_occupancy(resources):
     funcs, _ = resources
-    want = {"decompress_kernelILi2ELb0ELb0E": 5, "stats_kernelILi2ELb0ELb0E": 5, "pack_kernelILi2ELb0E": 5}
+    want = {"decompress_kernelILi2ELb0ELb0E": 5, "stats_kernelILi2ELb0ELi0E": 5, "pack_kernelILi2ELb0E": 5}
     for frag, occ in want.items():
         hits = [r for n, r in funcs.items() if frag in n]
         assert hits, frag
