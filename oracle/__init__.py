@@ -92,6 +92,12 @@ def lib():
         L.orc_mlp_predict.argtypes = [vp, vp]
         L.orc_features.restype = c_int
         L.orc_features.argtypes = [vp, u64, c_int, u32, vp, vp]
+        L.orc_bound32.restype = u64
+        L.orc_bound32.argtypes = [u64, c_int, u32, c_int]
+        L.orc_compress32.restype = i64
+        L.orc_compress32.argtypes = [vp, u64, c_int, u32, c_int, vp, u64]
+        L.orc_decompress32.restype = i64
+        L.orc_decompress32.argtypes = [vp, u64, vp, u64]
         _lib = L
     return _lib
 
@@ -242,6 +248,46 @@ def decompress(stream: bytes) -> np.ndarray:
     rc, out = decompress_rc(stream)
     if rc < 0:
         raise ValueError("oracle decompress failed: %d" % rc)
+    return out
+
+
+# ---- streams of 32-bit words ---------------------------------------------------------
+
+def bound32(n: int, w: int, L: int, variant: int) -> int:
+    return lib().orc_bound32(n, w, L, variant)
+
+
+def compress32(x: np.ndarray, L: int, variant: int) -> bytes:
+    """Stream of 32-bit words (variant 0, 8 or SELECT_EXHAUSTIVE) of a 1-D u8/u16/u32 array."""
+    x = np.ascontiguousarray(x)
+    w = _WIDTH[x.dtype]
+    cap = bound32(x.size, w, L, variant)
+    if cap == 0:
+        raise ValueError("invalid arguments")
+    out = np.zeros(cap, dtype=np.uint8)
+    rc = lib().orc_compress32(_ptr(x), x.size, w, L, variant, _ptr(out), cap)
+    if rc < 0:
+        raise ValueError("oracle compress32 failed: %d" % rc)
+    return out[:rc].tobytes()
+
+
+def decompress32_rc(stream: bytes, out_cap: int | None = None):
+    """Returns (rc, values) without raising; rc < 0 is an error code."""
+    buf = np.frombuffer(stream, dtype=np.uint8)
+    try:
+        n, w, L, tot = stream_info(stream)
+    except ValueError:
+        return -3, None
+    cap = n if out_cap is None else out_cap
+    out = np.zeros(max(cap, 1), dtype=_DTYPE[w])
+    rc = lib().orc_decompress32(_ptr(buf), buf.size, _ptr(out), cap)
+    return rc, (out[:n] if rc >= 0 else None)
+
+
+def decompress32(stream: bytes) -> np.ndarray:
+    rc, out = decompress32_rc(stream)
+    if rc < 0:
+        raise ValueError("oracle decompress32 failed: %d" % rc)
     return out
 
 

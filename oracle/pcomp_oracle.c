@@ -51,6 +51,7 @@ typedef unsigned __int128 u128;
 #define ORC_F_CLASS 1u /* per-block class array present */
 #define ORC_F_NE 2u    /* per-block excess-count array present */
 #define ORC_F_NE16 4u  /* excess counts stored as u16 (else u8) */
+#define ORC_F_W32 8u   /* payload of 32-bit words (orc_compress32) */
 
 /* ---------------------------------------------------------------------- */
 /* Sec. 3.1, Eq. (1): number of base-B digits that fit in one W-bit word.   */
@@ -860,4 +861,174 @@ int orc_features(const void *in, uint64_t n, int w, uint32_t L, float *x, uint64
     }
     free(d);
     return 0;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Streams of 32-bit words: the paper's own word, the unsigned int of       */
+/* Sec. 3.1 (Eq. (1) with capacity 2^32) and of the Sec. 3.2 series. Only   */
+/* the paper's two packings, t = 0: class 0 (basic) and class 8 (advanced). */
+/* Variants: 0, 8 (every block in that class) and ORC_SELECT_EXHAUSTIVE     */
+/* (per block the smaller of the two, ties to basic). Advanced packing is   */
+/* offered for u8 and u16 data only (every base then lies in [1, 2^16 + 1]);*/
+/* u32 data take variant 0.                                                 */
+/* Layout: that of orc_compress with flags ORC_F_W32 (plus ORC_F_CLASS for  */
+/* the exhaustive variant, no excess counts); the header's payload-word     */
+/* count, the tile index and the payload count 32-bit words, and the       */
+/* payload holds u32 words; total bytes = payload offset + 4 x words.       */
+/* ---------------------------------------------------------------------- */
+static int variant32_ok(int variant, int w)
+{
+    if (variant == 0) return 1;
+    return (variant == 8 || variant == ORC_SELECT_EXHAUSTIVE) && w < 4;
+}
+
+static unsigned stream_flags32(int variant)
+{
+    return ORC_F_W32 | (variant == ORC_SELECT_EXHAUSTIVE ? ORC_F_CLASS : 0);
+}
+
+/* Worst case: every block in at most ceil(L_b / (4 / w)) words (B <= 2^(8w)
+ * gives at least 32 / (8w) digits per word, and the advanced series never
+ * takes more words than the basic packing: each of its words closes p_i + 1
+ * >= k values). */
+uint64_t orc_bound32(uint64_t n, int w, uint32_t L, int variant)
+{
+    if (!(w == 1 || w == 2 || w == 4) || L == 0 || L > 65535 || !variant32_ok(variant, w)) return 0;
+    orc_layout lo;
+    layout_of(n, w, L, stream_flags32(variant), &lo);
+    uint64_t per = 4 / (uint64_t)w;
+    uint64_t words = 0;
+    if (lo.n_blocks) {
+        uint64_t last = n - (lo.n_blocks - 1) * L;
+        words = (lo.n_blocks - 1) * ((L + per - 1) / per) + (last + per - 1) / per;
+    }
+    return lo.off_payload + 4 * words;
+}
+
+int64_t orc_compress32(const void *in, uint64_t n, int w, uint32_t L, int variant, uint8_t *out, uint64_t cap)
+{
+    if (!(w == 1 || w == 2 || w == 4) || L == 0 || L > 65535 || !variant32_ok(variant, w)) return ORC_EINVAL;
+    if (n && !in) return ORC_EINVAL;
+    orc_layout lo;
+    unsigned flags = stream_flags32(variant);
+    layout_of(n, w, L, flags, &lo);
+    uint64_t nb = lo.n_blocks;
+    uint64_t *mins = (uint64_t *)calloc(nb + 1, sizeof(uint64_t));
+    uint64_t *Bs = (uint64_t *)calloc(nb + 1, sizeof(uint64_t));
+    int *cls = (int *)calloc(nb + 1, sizeof(int));
+    uint64_t *d = (uint64_t *)malloc(sizeof(uint64_t) * L);
+
+    /* Pass 1: per block min, B (Sec. 3.1) and the class. */
+    uint64_t total_words = 0;
+    for (uint64_t b = 0; b < nb; b++) {
+        uint64_t first = b * L;
+        uint64_t Lb = (n - first < L) ? (n - first) : L;
+        uint64_t vmin = UINT64_MAX, vmax = 0;
+        for (uint64_t j = 0; j < Lb; j++) {
+            uint64_t v = load_val(in, w, first + j);
+            if (v < vmin) vmin = v;
+            if (v > vmax) vmax = v;
+        }
+        uint64_t B = vmax - vmin + 1;
+        uint64_t w0 = orc_family_words(0, Lb, B, 32);
+        int c = variant == ORC_SELECT_EXHAUSTIVE ? (orc_family_words(1, Lb, B, 32) < w0 ? 8 : 0) : variant;
+        mins[b] = vmin;
+        Bs[b] = B;
+        cls[b] = c;
+        total_words += orc_family_words(c >> 3, Lb, B, 32);
+    }
+    uint64_t total = lo.off_payload + 4 * total_words;
+    if (total > cap || !out) {
+        free(mins); free(Bs); free(cls); free(d);
+        return ORC_ENOSPC;
+    }
+    memset(out, 0, lo.off_payload);
+    put_le(out + 0, ORC_MAGIC, 4);
+    put_le(out + 4, ORC_VERSION, 2);
+    out[6] = (uint8_t)w;
+    out[7] = (uint8_t)flags;
+    out[8] = (uint8_t)(variant == ORC_SELECT_EXHAUSTIVE ? 0 : variant);
+    out[9] = (uint8_t)(variant == ORC_SELECT_EXHAUSTIVE ? 1 : 0);
+    put_le(out + 12, L, 4);
+    put_le(out + 16, n, 8);
+    put_le(out + 24, nb, 8);
+    put_le(out + 32, lo.tile_blocks, 4);
+    put_le(out + 40, total_words, 8);
+    put_le(out + 48, total, 8);
+
+    /* Pass 2: block arrays and payload (each word stored as 4 bytes). */
+    uint64_t off = 0;
+    uint64_t *words = (uint64_t *)malloc(sizeof(uint64_t) * (L + 1));
+    for (uint64_t b = 0; b < nb; b++) {
+        if (b % lo.tile_blocks == 0) put_le(out + lo.off_index + 8 * (b / lo.tile_blocks), off, 8);
+        put_le(out + lo.off_min + (uint64_t)w * b, mins[b], w);
+        put_le(out + lo.off_range + (uint64_t)w * b, Bs[b] - 1, w);
+        if (flags & ORC_F_CLASS) out[lo.off_class + b] = (uint8_t)cls[b];
+        uint64_t first = b * L;
+        uint64_t Lb = (n - first < L) ? (n - first) : L;
+        for (uint64_t j = 0; j < Lb; j++) d[j] = load_val(in, w, first + j) - mins[b];
+        uint64_t nw = orc_family_pack(cls[b] >> 3, d, Lb, Bs[b], 32, words);
+        for (uint64_t i = 0; i < nw; i++) put_le(out + lo.off_payload + 4 * (off + i), words[i], 4);
+        off += nw;
+    }
+    free(words);
+    free(mins); free(Bs); free(cls); free(d);
+    return (int64_t)total;
+}
+
+int64_t orc_decompress32(const uint8_t *in, uint64_t in_size, void *out, uint64_t out_cap_values)
+{
+    uint64_t n, total;
+    int w;
+    uint32_t L;
+    int rc = orc_stream_info(in, in_size, &n, &w, &L, &total);
+    if (rc) return rc;
+    unsigned flags = in[7];
+    if ((flags & ~(ORC_F_W32 | ORC_F_CLASS)) || !(flags & ORC_F_W32)) return ORC_ECORRUPT;
+    int fixed = in[8];
+    orc_layout lo;
+    layout_of(n, w, L, flags, &lo);
+    if (get_le(in + 24, 8) != lo.n_blocks || get_le(in + 32, 4) != lo.tile_blocks) return ORC_ECORRUPT;
+    uint64_t pw = get_le(in + 40, 8);
+    if (total != lo.off_payload + 4 * pw || total > in_size) return ORC_ECORRUPT;
+    if (!(flags & ORC_F_CLASS) && !(fixed == 0 || fixed == 8)) return ORC_ECORRUPT;
+    if (n > out_cap_values) return ORC_ENOSPC;
+    if (n && !out) return ORC_EINVAL;
+    uint64_t *d = (uint64_t *)malloc(sizeof(uint64_t) * L);
+    uint64_t *words = (uint64_t *)malloc(sizeof(uint64_t) * (L + 1));
+    uint64_t off = 0;
+    int64_t result = (int64_t)n;
+    for (uint64_t b = 0; b < lo.n_blocks; b++) {
+        if (b % lo.tile_blocks == 0 && get_le(in + lo.off_index + 8 * (b / lo.tile_blocks), 8) != off) {
+            result = ORC_ECORRUPT;
+            break;
+        }
+        uint64_t vmin = get_le(in + lo.off_min + (uint64_t)w * b, w);
+        uint64_t B = get_le(in + lo.off_range + (uint64_t)w * b, w) + 1;
+        int c = (flags & ORC_F_CLASS) ? in[lo.off_class + b] : fixed;
+        uint64_t first = b * L;
+        uint64_t Lb = (n - first < L) ? (n - first) : L;
+        /* classes 0 and 8 only; advanced blocks need B <= 2^16 + 1 */
+        if (vmin + B - 1 > (w == 4 ? 0xFFFFFFFFull : (1ull << (8 * w)) - 1) || (c != 0 && c != 8) ||
+            (c == 8 && B > 65537)) {
+            result = ORC_ECORRUPT;
+            break;
+        }
+        uint64_t nw = orc_family_words(c >> 3, Lb, B, 32);
+        if (off + nw > pw) {
+            result = ORC_ECORRUPT;
+            break;
+        }
+        for (uint64_t i = 0; i < nw; i++) words[i] = get_le(in + lo.off_payload + 4 * (off + i), 4);
+        if (B <= 1)
+            for (uint64_t j = 0; j < Lb; j++) d[j] = 0;
+        else
+            orc_family_unpack(c >> 3, words, Lb, B, 32, d);
+        for (uint64_t j = 0; j < Lb; j++) store_val(out, w, first + j, d[j] + vmin);
+        off += nw;
+    }
+    if (result >= 0 && off != pw) result = ORC_ECORRUPT;
+    free(d);
+    free(words);
+    return result;
 }
