@@ -186,6 +186,30 @@ int pcomp_decompress_transposed(const void *d_in, size_t in_size, pcomp_dtype dt
 int pcomp_integrate(const void *d_in, pcomp_dtype dtype, uint64_t n_traces, uint32_t samples, uint32_t *d_out,
                     void *stream);
 
+/* ---- 32-bit words (Sec. 3.1-3.2 with the paper's unsigned int) -------------
+ * The paper packs into 32-bit unsigned ints: Eq. (1) and the series of Sec. 3.2
+ * with capacity 2^32 (read exactly: k = max{k : B^k <= 2^32}, as above for
+ * 2^64). These calls write and read v1 streams of 32-bit words: header flags
+ * bit 3 set, the header's payload-word count, the tile index and the payload
+ * in 32-bit words (u32, little-endian), total bytes = payload offset + 4 x
+ * words, no excess counts. Only the paper's two packings: variant 0 (basic,
+ * class 0), 8 (advanced, class 8) or PCOMP_SELECT_EXHAUSTIVE (per block the
+ * smaller of the two, ties to basic; flags bit 0 and the class array). The
+ * advanced tables cover B <= 2^16 + 1, so variants 8 and exhaustive take u8
+ * and u16 data only; u32 data take variant 0. block_len * dtype bytes <=
+ * 16384. Other rules, arguments and errors as pcomp_bound,
+ * pcomp_workspace_size, pcomp_compress (the error word is the first u32 of
+ * d_ws: bit 2 = a tile's payload would have passed the capacity) and
+ * pcomp_decompress_typed; PCOMP_EINVAL for an unsupported dtype / variant
+ * pair. The two stream kinds are not interchangeable: each decoder reports
+ * the other's streams PCOMP_ECORRUPT. */
+size_t pcomp_bound32(uint64_t n, pcomp_dtype dtype, uint32_t block_len, int variant);
+size_t pcomp_workspace_size32(uint64_t n, pcomp_dtype dtype, uint32_t block_len, int variant);
+int pcomp_compress32(const void *d_in, uint64_t n, pcomp_dtype dtype, uint32_t block_len, int variant, void *d_out,
+                     size_t out_capacity, uint64_t *d_out_size, void *d_ws, size_t ws_bytes, void *stream);
+int pcomp_decompress32(const void *d_in, size_t in_size, pcomp_dtype dtype, uint32_t block_len, void *d_out,
+                       size_t out_capacity, int32_t *d_status, void *stream);
+
 /* Host-only: reads n, dtype bytes and total stream size from a header that is
  * already in host memory (first 64 bytes of a stream). Returns PCOMP_OK or
  * PCOMP_ECORRUPT. */

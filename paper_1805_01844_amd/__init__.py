@@ -91,6 +91,14 @@ def lib():
         L.pcomp_mlp_adam.restype = i32
         L.pcomp_mlp_adam.argtypes = [vp, vp, vp, vp, u32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                      ctypes.c_float, vp]
+        L.pcomp_bound32.restype = sz
+        L.pcomp_bound32.argtypes = [u64, i32, u32, i32]
+        L.pcomp_workspace_size32.restype = sz
+        L.pcomp_workspace_size32.argtypes = [u64, i32, u32, i32]
+        L.pcomp_compress32.restype = i32
+        L.pcomp_compress32.argtypes = [vp, u64, i32, u32, i32, vp, sz, vp, vp, sz, vp]
+        L.pcomp_decompress32.restype = i32
+        L.pcomp_decompress32.argtypes = [vp, sz, i32, u32, vp, sz, vp, vp]
         _lib = L
     return _lib
 
@@ -221,6 +229,70 @@ def decompress(stream: torch.Tensor) -> torch.Tensor:
     st = int(status.item())
     if st != OK:
         raise PcompError(st, "pcomp_decompress (device status)")
+    return out[:n]
+
+
+# ---- streams of 32-bit words ---------------------------------------------------------------
+
+class Compressor32:
+    """Reusable buffers for streams of 32-bit words (``pcomp_compress32``): variant 0 (basic),
+    8 (advanced, u8/u16 data) or SELECT_EXHAUSTIVE (the smaller of the two per block)."""
+
+    def __init__(self, n: int, dtype: torch.dtype, block_len: int, variant: int, device="cuda"):
+        self.n, self.w, self.L, self.variant = int(n), _DT[dtype], int(block_len), int(variant)
+        cap = lib().pcomp_bound32(self.n, self.w, self.L, self.variant)
+        if cap == 0:
+            raise PcompError(EINVAL, "pcomp_bound32")
+        self.out = torch.empty(cap, dtype=torch.uint8, device=device)
+        ws = lib().pcomp_workspace_size32(self.n, self.w, self.L, self.variant)
+        self.ws = torch.empty(max(8, ws), dtype=torch.uint8, device=device)
+        self.size = torch.zeros(1, dtype=torch.int64, device=device)
+
+    def __call__(self, x: torch.Tensor) -> None:
+        _require(_is_values(x) and x.numel() == self.n and _DT[x.dtype] == self.w and x.device == self.out.device,
+                 "x is a contiguous CUDA tensor of the compressor's size, dtype and device")
+        rc = lib().pcomp_compress32(ctypes.c_void_p(x.data_ptr()), self.n, self.w, self.L, self.variant,
+                                    ctypes.c_void_p(self.out.data_ptr()), self.out.numel(),
+                                    ctypes.c_void_p(self.size.data_ptr()), ctypes.c_void_p(self.ws.data_ptr()),
+                                    self.ws.numel(), _stream_handle())
+        _check(rc, "pcomp_compress32")
+
+    def error_flag(self) -> int:
+        return int(self.ws[:4].view(torch.int32).item())
+
+    def stream(self) -> torch.Tensor:
+        n = int(self.size.item())
+        err = self.error_flag()
+        if err:
+            raise PcompError(EHIP, "pcomp_compress32 (device error word %d)" % err)
+        return self.out[:n]
+
+
+def compress32(x: torch.Tensor, block_len: int, variant: int = 0) -> torch.Tensor:
+    """Stream of 32-bit words of a contiguous u8/u16/u32 CUDA tensor (a u8 CUDA tensor)."""
+    x = x.contiguous().reshape(-1)
+    c = Compressor32(x.numel(), x.dtype, block_len, variant, device=x.device)
+    c(x)
+    return c.stream()
+
+
+def decompress32_into(stream: torch.Tensor, out: torch.Tensor, status: torch.Tensor, block_len: int) -> None:
+    """Enqueues decompression of a stream of 32-bit words into `out` (its dtype is the stream's)."""
+    _check_decode_args(stream, out, status)
+    rc = lib().pcomp_decompress32(ctypes.c_void_p(stream.data_ptr()), stream.numel(), _DT[out.dtype],
+                                  int(block_len), ctypes.c_void_p(out.data_ptr()), out.numel(),
+                                  ctypes.c_void_p(status.data_ptr()), _stream_handle())
+    _check(rc, "pcomp_decompress32")
+
+
+def decompress32(stream: torch.Tensor) -> torch.Tensor:
+    n, w, L, tot = stream_info(stream)
+    out = torch.empty(max(n, 1), dtype=_TORCH[w], device=stream.device)
+    status = torch.zeros(1, dtype=torch.int32, device=stream.device)
+    decompress32_into(stream, out, status, L)
+    st = int(status.item())
+    if st != OK:
+        raise PcompError(st, "pcomp_decompress32 (device status)")
     return out[:n]
 
 

@@ -7,7 +7,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpcomp.so")
-SOURCES = ["compress.hip", "decompress.hip", "mlp.hip", "integrate.hip", "capi.hip", "atlas.cpp"]
+SOURCES = ["compress.hip", "decompress.hip", "mlp.hip", "integrate.hip", "words32.hip", "capi.hip", "atlas.cpp"]
 
 HIPCC_FLAGS = [
     "-O3",

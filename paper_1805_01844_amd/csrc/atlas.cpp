@@ -115,6 +115,56 @@ void build_base(uint64_t B, BaseDesc &D, std::vector<AtlasEntry> &ent) {
     }
 }
 
+// The same for 32-bit words (capacity 2^32): k, the two quotients, the cycle form, and binary64
+// reciprocals of B and of every R_i.
+const u128 kTwo32 = ((u128)1) << 32;
+
+uint32_t k32_host(uint64_t B) {
+    u128 acc = 1;
+    uint32_t k = 0;
+    while (acc * B <= kTwo32) {
+        acc *= B;
+        k++;
+    }
+    return k;
+}
+
+void build_base32(uint64_t B, BaseDesc32 &D, std::vector<AtlasEntry32> &ent) {
+    D.rB = 1.0 / (double)B;  // IEEE division: correctly rounded
+    D.k = k32_host(B);
+    u128 bk = 1;
+    for (uint32_t i = 0; i + 1 < D.k; i++) bk *= B;
+    D.Qk1 = (uint64_t)(kTwo32 / bk);
+    bk *= B;
+    D.Qk = (uint64_t)(kTwo32 / bk);
+    D.off = (uint32_t)ent.size();
+    std::unordered_map<uint64_t, uint32_t> seen;
+    uint64_t s = 1;
+    uint32_t q = 0, t = 0;
+    for (;;) {
+        auto it = seen.find(s);
+        if (it != seen.end()) {
+            D.mu = (uint16_t)it->second;
+            D.lam = (uint16_t)(t - it->second);
+            D.V = q - ent[D.off + it->second].q;
+            return;
+        }
+        seen[s] = t;
+        const uint32_t p = (s <= D.Qk) ? D.k : D.k - 1;
+        const uint64_t R = ((p == D.k) ? D.Qk : D.Qk1) / s;
+        AtlasEntry32 e;
+        e.rR = 1.0 / (double)R;
+        e.s = (uint32_t)s;
+        e.R = (uint32_t)R;
+        e.q = q;
+        e.p = p;
+        ent.push_back(e);
+        q += p + 1;
+        s = (B + R - 1) / R;
+        t++;
+    }
+}
+
 struct DeviceTables {
     bool ready = false;
     DevTables t{};
@@ -124,6 +174,8 @@ std::mutex g_mu;
 DeviceTables g_dev[64];
 std::vector<BaseDesc> *g_desc = nullptr;
 std::vector<AtlasEntry> *g_ent = nullptr;
+std::vector<BaseDesc32> *g_desc32 = nullptr;
+std::vector<AtlasEntry32> *g_ent32 = nullptr;
 uint64_t g_kmax[65];
 
 void build_host_tables() {
@@ -153,6 +205,12 @@ void build_host_tables() {
         }
         g_kmax[k] = lo;
     }
+    auto *desc32 = new std::vector<BaseDesc32>(kAtlasDirect + 1);
+    auto *ent32 = new std::vector<AtlasEntry32>();
+    ent32->reserve(400000);
+    for (uint32_t B = 2; B <= kAtlasDirect; B++) build_base32(B, (*desc32)[B], *ent32);
+    g_desc32 = desc32;
+    g_ent32 = ent32;
     g_desc = desc;
     g_ent = ent;
 }
@@ -178,6 +236,14 @@ int tables_for_current_device(DevTables *out) {
         if (hipMemcpy(pd, g_desc->data(), bd, hipMemcpyHostToDevice) != hipSuccess) return PCOMP_EHIP;
         if (hipMemcpy(pe, g_ent->data(), be, hipMemcpyHostToDevice) != hipSuccess) return PCOMP_EHIP;
         if (hipMemcpy(pk, g_kmax, sizeof(g_kmax), hipMemcpyHostToDevice) != hipSuccess) return PCOMP_EHIP;
+        void *pd32 = nullptr, *pe32 = nullptr;
+        const size_t bd32 = sizeof(BaseDesc32) * g_desc32->size(), be32 = sizeof(AtlasEntry32) * g_ent32->size();
+        if (hipMalloc(&pd32, bd32) != hipSuccess) return PCOMP_EHIP;
+        if (hipMalloc(&pe32, be32) != hipSuccess) return PCOMP_EHIP;
+        if (hipMemcpy(pd32, g_desc32->data(), bd32, hipMemcpyHostToDevice) != hipSuccess) return PCOMP_EHIP;
+        if (hipMemcpy(pe32, g_ent32->data(), be32, hipMemcpyHostToDevice) != hipSuccess) return PCOMP_EHIP;
+        D.t.desc32 = (const BaseDesc32 *)pd32;
+        D.t.ent32 = (const AtlasEntry32 *)pe32;
         D.t.desc = (const BaseDesc *)pd;
         D.t.ent = (const AtlasEntry *)pe;
         D.t.kmax = (const uint64_t *)pk;
@@ -259,5 +325,19 @@ extern "C" int pcomp_atlas_words(uint64_t B, uint32_t n, uint32_t *words) {
     if (idx < 0 || n == 0) return PCOMP_EINVAL;
     const BaseDesc &D = (*g_desc)[idx];
     *words = adv_words_cycle(g_ent->data() + D.off, D, n);
+    return PCOMP_OK;
+}
+
+// Host-side: advanced word count of n digits of base B <= 2^16 + 1 in 32-bit words, from the
+// cycle form of that word size.
+extern "C" int pcomp_atlas32_words(uint64_t B, uint32_t n, uint32_t *words) {
+    using namespace pcomp;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        build_host_tables();
+    }
+    if (B < 2 || B > kAtlasDirect || n == 0 || !words) return PCOMP_EINVAL;
+    const BaseDesc32 &D = (*g_desc32)[B];
+    *words = adv_words_cycle(g_ent32->data() + D.off, D, n);
     return PCOMP_OK;
 }

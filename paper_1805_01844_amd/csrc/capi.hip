@@ -28,6 +28,11 @@ int launch_mlp_adam(float *prm, const float *grad, float *m, float *v, uint32_t 
 int launch_decompress_batch(const BatchPlanHeader &ph, const SegDesc *d_segs, const uint32_t *d_tile_seg,
                             const void *d_in, size_t in_size, const uint64_t *d_seg_offsets, int32_t *d_status,
                             uint32_t grid, hipStream_t st);
+uint64_t w32_ws_bytes(const Layout &lo);
+int launch_compress32(const void *d_in, const Layout &lo, int variant, void *d_out, uint64_t out_cap,
+                      uint64_t *d_out_size, void *ws, hipStream_t st);
+int launch_decompress32(const void *d_in, size_t in_size, void *d_out, size_t out_capacity, int32_t *d_status,
+                        int w, uint32_t L, hipStream_t st);
 }  // namespace pcomp
 
 using namespace pcomp;
@@ -373,4 +378,64 @@ extern "C" int pcomp_integrate(const void *d_in, pcomp_dtype dtype, uint64_t n_t
     const uint64_t vmax = w == 4 ? 0xFFFFFFFFull : (1ull << (8 * w)) - 1;
     if ((uint64_t)samples * vmax > 0xFFFFFFFFull || (uint64_t)samples * w > 16384) return PCOMP_EINVAL;
     return launch_integrate(d_in, w, n_traces, samples, d_out, (hipStream_t)stream);
+}
+
+// ---- streams of 32-bit words --------------------------------------------------------------
+namespace {
+bool variant32_ok(int v, int w) { return v == 0 || ((v == 8 || v == PCOMP_SELECT_EXHAUSTIVE) && w < 4); }
+unsigned flags32_of(int v) { return kFlagW32 | (v == PCOMP_SELECT_EXHAUSTIVE ? kFlagClass : 0u); }
+bool args32_ok(int w, uint32_t L, int v) {
+    return dtype_ok(w) && L != 0 && L <= 65535 && (uint64_t)L * w <= kTileBytes && variant32_ok(v, w);
+}
+
+// Every block at most ceil(L_b / (4 / w)) words: B <= 2^(8w) gives at least 32 / (8w) digits per
+// 32-bit word, and the advanced series never takes more words than the basic packing.
+uint64_t bound32_of(const Layout &lo) {
+    const uint64_t per = 4 / lo.w;
+    uint64_t words = 0;
+    if (lo.n_blocks) {
+        const uint64_t last = lo.n - (lo.n_blocks - 1) * lo.L;
+        words = (lo.n_blocks - 1) * ((lo.L + per - 1) / per) + (last + per - 1) / per;
+    }
+    return lo.off_payload + 4 * words;
+}
+}  // namespace
+
+extern "C" size_t pcomp_bound32(uint64_t n, pcomp_dtype dtype, uint32_t block_len, int variant) {
+    const int w = (int)dtype;
+    if (!args32_ok(w, block_len, variant)) return 0;
+    Layout lo;
+    make_layout(n, w, block_len, flags32_of(variant), lo);
+    return (size_t)bound32_of(lo);
+}
+
+extern "C" size_t pcomp_workspace_size32(uint64_t n, pcomp_dtype dtype, uint32_t block_len, int variant) {
+    const int w = (int)dtype;
+    if (!args32_ok(w, block_len, variant)) return 0;
+    Layout lo;
+    make_layout(n, w, block_len, flags32_of(variant), lo);
+    return (size_t)w32_ws_bytes(lo);
+}
+
+extern "C" int pcomp_compress32(const void *d_in, uint64_t n, pcomp_dtype dtype, uint32_t block_len, int variant,
+                                void *d_out, size_t out_capacity, uint64_t *d_out_size, void *d_ws, size_t ws_bytes,
+                                void *stream) {
+    const int w = (int)dtype;
+    if (!args32_ok(w, block_len, variant)) return PCOMP_EINVAL;
+    if ((n && !d_in) || !d_out || !d_out_size || !d_ws) return PCOMP_EINVAL;
+    if (((uintptr_t)d_out & 7) || ((uintptr_t)d_ws & 7) || ((uintptr_t)d_in % w)) return PCOMP_EINVAL;
+    Layout lo;
+    make_layout(n, w, block_len, flags32_of(variant), lo);
+    if (out_capacity < bound32_of(lo)) return PCOMP_ENOSPC;
+    if (ws_bytes < w32_ws_bytes(lo)) return PCOMP_ENOWS;
+    return launch_compress32(d_in, lo, variant, d_out, out_capacity, d_out_size, d_ws, (hipStream_t)stream);
+}
+
+extern "C" int pcomp_decompress32(const void *d_in, size_t in_size, pcomp_dtype dtype, uint32_t block_len,
+                                  void *d_out, size_t out_capacity, int32_t *d_status, void *stream) {
+    const int w = (int)dtype;
+    if (!args32_ok(w, block_len, 0)) return PCOMP_EINVAL;
+    if (!d_in || !d_status || (out_capacity && !d_out)) return PCOMP_EINVAL;
+    if (((uintptr_t)d_in & 7) || ((uintptr_t)d_out % w)) return PCOMP_EINVAL;
+    return launch_decompress32(d_in, in_size, d_out, out_capacity, d_status, w, block_len, (hipStream_t)stream);
 }

@@ -230,30 +230,6 @@ __device__ __forceinline__ void pack_part(const DevTables &T, const SizeCtx &C, 
     if (Wide) pack_adv_slow(T, base, n, nwords, i0, G, dst, get);
 }
 
-// Stages the input of one tile in LDS (16-byte chunks; the partial chunks at the ends by
-// element) and returns the LDS address of its first value.
-template <int W>
-__device__ __forceinline__ const typename Elem<W>::T *stage_tile(const uint8_t *in, uint64_t v0, uint32_t nvt,
-                                                                  uint4 *s_raw) {
-    typedef typename Elem<W>::T V;
-    uint8_t *s_bytes = (uint8_t *)s_raw;
-    const uintptr_t addr = (uintptr_t)(in + v0 * W);
-    const uint32_t head = (uint32_t)(addr & 15);
-    const uint8_t *gbase = (const uint8_t *)(addr - head);
-    const uint32_t span = head + nvt * W;
-    const uint32_t nchunks = (span + 15) >> 4;
-    for (uint32_t c = threadIdx.x; c < nchunks; c += kThreads) {
-        const uint32_t cb = c << 4;
-        if (cb >= head && cb + 16 <= span) {
-            s_raw[c] = *(const uint4 *)(gbase + cb);
-        } else {
-            const uint32_t e0 = cb > head ? cb : head, e1 = cb + 16 < span ? cb + 16 : span;
-            for (uint32_t b = e0; b < e1; b += W) *(V *)(s_bytes + b) = *(const V *)(gbase + b);
-        }
-    }
-    return (const V *)(s_bytes + head);
-}
-
 // Stages a tile of a time-major segment: value v0 + j of the stream is gathered from the
 // element of the caller's matrices it stands for (one load per value).
 template <int W>
@@ -1045,6 +1021,22 @@ void launch_tiles(bool stats, bool persist, uint32_t grid, size_t dyn, const Com
         pack_kernel<W, true><<<grid, kThreads, dyn, st>>>(b);
     } else {
         pack_kernel<W, false><<<grid, kThreads, dyn, st>>>(b);
+    }
+}
+
+// Exclusive prefix of n_tiles u32 totals by the two scan launches: prefix[t] for every tile
+// and prefix[n_tiles] = their sum (nothing is written for n_tiles = 0). `sums` holds
+// tile_scan_runs(n_tiles) u64. Used by the streams of 32-bit words.
+uint64_t tile_scan_runs(uint64_t n_tiles) { return (n_tiles + kScanTiles - 1) / kScanTiles; }
+void launch_tile_scan(uint32_t *tile_words, uint64_t *prefix, uint64_t *sums, uint64_t n_tiles, hipStream_t st) {
+    CompressArgs a{};
+    a.tile_words = tile_words;
+    a.prefix = prefix;
+    a.n_tiles = n_tiles;
+    const uint32_t runs = (uint32_t)tile_scan_runs(n_tiles);
+    if (runs > 0) {
+        scan_sums_kernel<<<runs, kThreads, 0, st>>>(a, sums);
+        scan_prefix_kernel<<<runs, kThreads, 0, st>>>(a, sums);
     }
 }
 

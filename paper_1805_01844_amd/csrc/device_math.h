@@ -188,7 +188,9 @@ __device__ __forceinline__ uint32_t adv_words_slow(const SlowBase sb, uint32_t n
 
 // c_t = q_t + p_t (values reached by word t, 0-based) from the cycle form: entries
 // 0 .. mu+lam-1 are stored, and c_{t + lam} = c_t + V for t >= mu.
-__host__ __device__ __forceinline__ uint32_t adv_reach(const AtlasEntry *E, const BaseDesc &D, uint32_t t) {
+// (Entries and descriptors of either word size.)
+template <typename Entry, typename Desc>
+__host__ __device__ __forceinline__ uint32_t adv_reach(const Entry *E, const Desc &D, uint32_t t) {
     const uint32_t tot = D.mu + D.lam;
     if (t < tot) return E[t].q + E[t].p;
     const uint32_t c = udiv_small(t - D.mu, D.lam);
@@ -200,7 +202,8 @@ __host__ __device__ __forceinline__ uint32_t adv_reach(const AtlasEntry *E, cons
 // k or k + 1 values (p_t is k - 1 or k, plus the split value) and the first takes k,
 // so (t+1) k <= c_t <= (t+1)(k+1) - 1: the answer lies in
 // [ceil((n+1)/(k+1)) - 1, ceil(n/k) - 1], a range of about n / k^2 words.
-__host__ __device__ inline uint32_t adv_words_cycle(const AtlasEntry *E, const BaseDesc &D, uint32_t n) {
+template <typename Entry, typename Desc>
+__host__ __device__ inline uint32_t adv_words_cycle(const Entry *E, const Desc &D, uint32_t n) {
     const uint32_t k = D.k;
     if (n <= k) return 1;
     uint32_t lo = udiv_small(n + 1 + k, k + 1) - 1;  // ceil((n+1)/(k+1)) - 1

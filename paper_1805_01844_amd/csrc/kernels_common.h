@@ -177,6 +177,30 @@ struct TmCursor {
     }
 };
 
+// Stages the input of one tile in LDS (16-byte chunks; the partial chunks at the ends by
+// element) and returns the LDS address of its first value.
+template <int W>
+__device__ __forceinline__ const typename Elem<W>::T *stage_tile(const uint8_t *in, uint64_t v0, uint32_t nvt,
+                                                                  uint4 *s_raw) {
+    typedef typename Elem<W>::T V;
+    uint8_t *s_bytes = (uint8_t *)s_raw;
+    const uintptr_t addr = (uintptr_t)(in + v0 * W);
+    const uint32_t head = (uint32_t)(addr & 15);
+    const uint8_t *gbase = (const uint8_t *)(addr - head);
+    const uint32_t span = head + nvt * W;
+    const uint32_t nchunks = (span + 15) >> 4;
+    for (uint32_t c = threadIdx.x; c < nchunks; c += kThreads) {
+        const uint32_t cb = c << 4;
+        if (cb >= head && cb + 16 <= span) {
+            s_raw[c] = *(const uint4 *)(gbase + cb);
+        } else {
+            const uint32_t e0 = cb > head ? cb : head, e1 = cb + 16 < span ? cb + 16 : span;
+            for (uint32_t b = e0; b < e1; b += W) *(V *)(s_bytes + b) = *(const V *)(gbase + b);
+        }
+    }
+    return (const V *)(s_bytes + head);
+}
+
 // A pointer into LDS, as the compiler sees it: a staged tile chosen among several buffers can
 // lose that address space, and its reads would then take flat addressing.
 template <typename T>

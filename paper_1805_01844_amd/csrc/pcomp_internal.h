@@ -16,6 +16,7 @@ constexpr uint32_t kThreads = 256;  // threads per workgroup of every kernel
 constexpr uint32_t kCtxBytes = 1024;  // workspace slot of the per-launch size tables
 
 constexpr unsigned kFlagClass = 1, kFlagNe = 2, kFlagNe16 = 4;
+constexpr unsigned kFlagW32 = 8;  // payload of 32-bit words (streams of pcomp_compress32)
 
 // Bases with a precomputed advanced-method schedule: every B in [2, kAtlasDirect]
 // plus 2^j + 1 for j = 17..31 (the main base T + 1 of threshold classes on wide data).
@@ -70,9 +71,33 @@ struct AtlasEntry {
     uint32_t p;   // p_i
 };
 
+// The series of Sec. 3.2 with 32-bit words (capacity 2^32), for every B in [2, 2^16 + 1]:
+// p_i = k if s_i <= Qk else k - 1 (k = max{k : B^k <= 2^32}), R_i = floor(Q_{p_i} / s_i),
+// next state ceil(B / R_i), in the same cycle form. Every word is below 2^32, so its
+// divisions are binary64 ones by the stored reciprocals (exact below 2^51, as in digit_off).
+struct BaseDesc32 {
+    double rB;     // 1 / B rounded to nearest
+    uint64_t Qk;   // floor(2^32 / B^k)
+    uint64_t Qk1;  // floor(2^32 / B^(k-1))
+    uint32_t k;    // digits per 32-bit word
+    uint32_t off;  // first AtlasEntry32
+    uint32_t V;    // values consumed by one cycle
+    uint16_t mu, lam;
+};
+
+struct AtlasEntry32 {
+    double rR;    // 1 / R_i rounded to nearest
+    uint32_t s;   // s_i = R'_{i-1}
+    uint32_t R;   // R_i
+    uint32_t q;   // q_i
+    uint32_t p;   // p_i
+};
+
 struct DevTables {
     const BaseDesc *desc;    // [kAtlasBases]
     const AtlasEntry *ent;   // entries of every base
+    const BaseDesc32 *desc32;   // [kAtlasDirect + 1]: 32-bit words
+    const AtlasEntry32 *ent32;  // their entries
     const uint64_t *kmax;    // [65]: kmax[k] = largest B with B^k <= 2^64 (kmax[1] = UINT64_MAX)
     const uint8_t *ktab;     // [kAtlasDirect + 1]: k(B) for every B <= 2^16 + 1 (0 for B < 2)
 };

@@ -34,10 +34,11 @@ def tile_parts(buf: np.ndarray, meta: dict, t: int):
     idx = buf[o["index"]:o["index"] + 8 * meta["ntiles"]].view(np.uint64)
     p0 = int(idx[t])
     p1 = int(idx[t + 1]) if t + 1 < meta["ntiles"] else meta["pw"]
+    wb = 4 if meta["flags"] & 8 else 8  # bytes per payload word (flags bit 3: 32-bit words)
     parts = {
         "min": buf[o["min"] + w * b0:o["min"] + w * b1].tobytes(),
         "range": buf[o["range"] + w * b0:o["range"] + w * b1].tobytes(),
-        "payload": buf[o["payload"] + 8 * p0:o["payload"] + 8 * p1].tobytes(),
+        "payload": buf[o["payload"] + wb * p0:o["payload"] + wb * p1].tobytes(),
     }
     if meta["flags"] & 1:
         parts["class"] = buf[o["class"] + b0:o["class"] + b1].tobytes()

@@ -14,7 +14,7 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_1805_01844_amd", "csrc")
-SOURCES = ["compress.hip", "decompress.hip", "mlp.hip", "integrate.hip", "capi.hip"]
+SOURCES = ["compress.hip", "decompress.hip", "mlp.hip", "integrate.hip", "words32.hip", "capi.hip"]
 
 
 def _compile(src, tmp):

@@ -96,6 +96,33 @@ def test_cycle_form_word_counts_match_oracle(pc, orc):
             assert out.value == orc.adv_words(n, B), (B, n)
 
 
+def test_cycle_form_word_counts_32bit_words_match_oracle(pc, orc):
+    # the tables of 32-bit words: word counts of the series with capacity 2^32, for every base
+    # in steps and the ends of the range, against the oracle's walk of the series
+    import ctypes
+    L = pc.lib()
+    L.pcomp_atlas32_words.restype = ctypes.c_int
+    L.pcomp_atlas32_words.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_void_p]
+    bases = list(range(2, 400)) + list(range(400, 65538, 97)) + [65535, 65536, 65537]
+    out = ctypes.c_uint32()
+    for B in bases:
+        for n in [1, 2, 3, 7, 40, 41, 154, 1000, 4096, 16384]:
+            assert L.pcomp_atlas32_words(B, n, ctypes.byref(out)) == 0
+            assert out.value == orc.adv_words(n, B, 32), (B, n)
+    assert L.pcomp_atlas32_words(65538, 10, ctypes.byref(out)) != 0
+
+
+@pytest.mark.parametrize("w,L", [(1, 1), (1, 1024), (2, 40), (2, 1024), (4, 256), (4, 4096)])
+@pytest.mark.parametrize("variant", [0, 8, 0x100])
+def test_bound32_matches_oracle(pc, orc, w, L, variant):
+    lib = pc.lib()
+    for n in [0, 1, L - 1, L, 10 * L + 3, 123457]:
+        want = orc.bound32(n, w, L, variant)
+        assert lib.pcomp_bound32(n, w, L, variant) == want
+        assert (lib.pcomp_workspace_size32(n, w, L, variant) >= 8) == (want > 0)
+    assert lib.pcomp_bound32(10, 2, 40, 3) == 0 and lib.pcomp_bound32(10, 2, 0, 0) == 0
+
+
 def _segs(pc, spec):
     arr = (pc._Segment * len(spec))()
     for i, (w, n) in enumerate(spec):
