@@ -355,6 +355,44 @@ def time_major_leg(x, L: int, variant: int, reps: int = 5):
             "decompress_GBps": round(nbytes / td / 1e9, 1), "roundtrip_bit_exact": True}
 
 
+def words32_leg(x, L: int, reps: int = 10):
+    """Streams of 32-bit words (the paper's unsigned int: Sec. 3.1 and 3.2 with capacity 2^32) of
+    the camera workload, basic, advanced and the smaller of the two per block, beside the
+    64-bit streams (their ratio for the same variants)."""
+    import torch
+
+    import paper_1805_01844_amd as pc
+
+    xf = x.reshape(-1)
+    n = xf.numel()
+    nbytes = n * 2
+    out = torch.empty_like(xf)
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    res = {"workload": "same camera events, blocks of %d, payload of 32-bit words" % L}
+    for name, v in (("basic", 0), ("advanced", 8), ("exhaustive", pc.SELECT_EXHAUSTIVE)):
+        comp = pc.Compressor32(n, torch.uint16, L, v, device="cuda")
+        comp(xf)
+        sl = int(comp.size.item())
+        s = comp.out[:sl]
+        tc, td = _time_pair(lambda: comp(xf), lambda: pc.decompress32_into(s, out, st, L), reps)
+        assert comp.error_flag() == 0 and int(comp.size.item()) == sl
+        out.fill_(0x5A5A)
+        pc.decompress32_into(s, out, st, L)
+        assert int(st.item()) == 0 and torch.equal(out.view(torch.int16), xf.view(torch.int16))
+        c64 = pc.Compressor(n, torch.uint16, L, v, device="cuda")
+        c64(xf)
+        r64 = nbytes / int(c64.size.item())
+        del c64
+        alg = nbytes + sl
+        res[name] = {"ratio": round(nbytes / sl, 4), "ratio_64bit_words": round(r64, 4),
+                     "compress_GBps": round(nbytes / tc / 1e9, 1), "decompress_GBps": round(nbytes / td / 1e9, 1),
+                     "roundtrip_bit_exact": True, "roofline_compress": _roofline(alg, tc),
+                     "roofline_decompress": _roofline(alg, td)}
+        del comp, s
+        torch.cuda.empty_cache()
+    return res
+
+
 def integrated_leg(x, reps: int = 10):
     """Integrated signal (Sec. 4.3.2): per-pixel sums of the camera events made on the GPU (u32),
     then compressed one event per block (L = 1855) with exhaustive choice."""
@@ -554,6 +592,7 @@ def main():
     if not args.no_extras:
         res["latency_tiny"] = latency_leg()
         res["time_major"] = time_major_leg(x, L, variant)
+        res["words32"] = words32_leg(x, L)
         res["integrated"] = integrated_leg(x)
         res["poly_lzma"] = poly_lzma_leg([e for e in x[:400].cpu()], L, variant)
     del comp, out, stream
