@@ -110,14 +110,30 @@ __device__ __forceinline__ void write_header(uint8_t *s, const Layout &lo, int v
 
 // Advanced part whose base is outside the tables: the state of word i depends on every
 // word before it, so each lane of the group walks the series itself and packs its own
-// words i0, i0 + G, ... (G a power of two).
+// words i0, i0 + G, ... (G a power of two). Once the walk finds the series' period, whole
+// periods before the lane's next word are skipped.
 template <typename Get>
 __device__ __forceinline__ void pack_adv_slow(const DevTables &T, uint64_t base, uint32_t n, uint32_t nwords,
                                               uint32_t i0, uint32_t G, uint64_t *dst, Get get) {
     const SlowBase sb = slow_base(T, base);
     uint64_t s = 1, rp = 0;  // carried base R'_{i-1} and top part r'_{i-1} of the split value
-    uint32_t q = 0;
+    uint32_t q = 0, p_prev = 0;
+    uint64_t R_prev = 1;
+    SeriesCycle cyc;
     for (uint32_t wi = 0; wi < nwords; wi++) {
+        if (cyc.found) {
+            const uint32_t target = next_own_word(wi, i0, G);
+            if (target >= nwords) break;
+            if (target - wi >= cyc.lam) {
+                const uint32_t c = udiv_small(target - wi, cyc.lam);
+                wi += c * cyc.lam;
+                q += c * cyc.V;
+                // word wi - 1 has the state of the word it replaces: the same p and R
+                const uint32_t xq = q - 1;  // q_{wi-1} + p_{wi-1}
+                const uint64_t x = xq < n ? get(xq) : 0;
+                rp = R_prev <= x ? udiv53(x, R_prev) : 0;
+            }
+        }
         uint32_t p;
         uint64_t R;
         slow_word_fast(sb, s, p, R);
@@ -135,9 +151,12 @@ __device__ __forceinline__ void pack_adv_slow(const DevTables &T, uint64_t base,
         }
         if (mine) dst[wi] = acc * R + r;
         rp = top;
+        p_prev = p;
+        R_prev = R;
         if (q + p >= n) break;
         s = slow_next(sb, R);
         q += p + 1;
+        cyc.step(s, q);
     }
 }
 

@@ -93,7 +93,8 @@ static_assert(sizeof(DecShared) <= 32768, "five workgroups per CU need at most 3
 
 // Advanced part whose base is outside the tables: each lane of the group walks the series
 // itself (the state of word i depends on every word before it) and decodes its own words
-// i0, i0 + G, ... (G a power of two), including the value split at the end of each.
+// i0, i0 + G, ... (G a power of two), including the value split at the end of each. Once the
+// walk finds the series' period, whole periods before the lane's next word are skipped.
 template <typename V, bool kOne = false, typename Src, typename Dst>
 __device__ __forceinline__ void unpack_adv_slow(const DevTables &T, uint64_t base, uint32_t n, uint32_t nwords,
                                                 uint32_t i0, uint32_t G, Src src, Dst dst, uint32_t add) {
@@ -102,11 +103,24 @@ __device__ __forceinline__ void unpack_adv_slow(const DevTables &T, uint64_t bas
     uint32_t q = 0, p;
     uint64_t R;
     slow_word_fast(sb, 1, p, R);
+    SeriesCycle cyc;
     for (uint32_t wi = 0; wi < nwords; wi++) {
+        if (cyc.found) {
+            const uint32_t target = next_own_word(wi, i0, G);
+            if (target >= nwords) break;
+            if (target - wi >= cyc.lam) {
+                const uint32_t c = udiv_small(target - wi, cyc.lam);
+                wi += c * cyc.lam;
+                q += c * cyc.V;
+            }
+        }
         const bool last = (q + p >= n) || wi + 1 >= nwords;
         uint32_t p1 = 0;
-        uint64_t R1 = 1;
-        if (!last) slow_word_fast(sb, slow_next(sb, R), p1, R1);
+        uint64_t R1 = 1, s1 = 1;
+        if (!last) {
+            s1 = slow_next(sb, R);
+            slow_word_fast(sb, s1, p1, R1);
+        }
         if (((wi - i0) & (G - 1)) == 0 && wi >= i0) {
             uint64_t r;
             uint64_t X = udiv64_48(src(wi), R, r);  // word = (r'_{i-1} B^p + digits) R + r
@@ -127,6 +141,7 @@ __device__ __forceinline__ void unpack_adv_slow(const DevTables &T, uint64_t bas
         q += p + 1;
         p = p1;
         R = R1;
+        cyc.step(s1, q);
     }
 }
 

@@ -152,6 +152,34 @@ __device__ __forceinline__ uint64_t slow_next(const SlowBase &sb, uint64_t R) {
     return R >= sb.B ? 1 : udiv53(sb.B - 1, R) + 1;
 }
 
+// Brent's cycle search over the carried base of the series (Sec. 3.2): s_t, the state of word
+// t, fixes every word after it, so once s_t = s_{t - lam} the series repeats with period lam,
+// V values per period, from word t - lam on. step() takes the state and q of each next word.
+struct SeriesCycle {
+    uint64_t s_mark;
+    uint32_t q_mark, power, lam, V;
+    bool found;
+    __device__ __forceinline__ SeriesCycle() : s_mark(1), q_mark(0), power(1), lam(0), V(0), found(false) {}
+    __device__ __forceinline__ void step(uint64_t s, uint32_t q) {
+        if (found) return;
+        lam++;
+        if (s == s_mark) {
+            found = true;
+            V = q - q_mark;
+        } else if (lam == power) {
+            s_mark = s;
+            q_mark = q;
+            power <<= 1;
+            lam = 0;
+        }
+    }
+};
+
+// The first of a lane's words i0, i0 + G, ... (G a power of two) at or after word wi.
+__device__ __forceinline__ uint32_t next_own_word(uint32_t wi, uint32_t i0, uint32_t G) {
+    return wi <= i0 ? i0 : i0 + ((wi - i0 + G - 1) & ~(G - 1));
+}
+
 // Word count of the series (Sec. 3.2) for n digits: walk it word by word. The carried base
 // s_t determines everything after word t, so once Brent's cycle search finds s_t = s_{t-lam}
 // the series repeats with period lam from there, consuming V = q_t - q_{t-lam} values per
