@@ -32,7 +32,9 @@
 namespace pcomp {
 
 // Parameters of the learned class selector on this device (pcomp_set_model).
-__constant__ float c_model[kMlpParams];
+__constant__ __align__(16) float c_model[kMlpParams];
+static_assert(kMlpW2 % 4 == 0 && kMlpB2 % 4 == 0 && kMlpOut % 4 == 0 && kMlpHid == 4 * kMlpOut,
+              "the statistics kernel copies the parameters in quads, W2's quad j of row k to j ^ k");
 constexpr uint32_t kFeatWords = 11;  // per block in LDS: 16 16-bit counts, min, max, L_b
 constexpr uint32_t kExcBytes = 2048;  // compaction buffer of a tile's excess lists
 constexpr uint32_t kAdvTab = kAtlasDirect + 1;  // entries of a full-block word table (bases 0 .. 2^16 + 1)
@@ -370,7 +372,7 @@ __global__ __launch_bounds__(kThreads) void stats_kernel(CompressArgs a) {
     // the selector's parameters, per workgroup: W1, b1 and b2 (at kMlpW2) in s_model; W2 in s_w2s,
     // row k holding W2[k][j] at column j ^ 4k, so that the 16 lanes that score the 16 classes read
     // their rows' quads j .. j + 3 from 16 different bank groups
-    __shared__ float s_model[kLearn ? kMlpW2 + kMlpOut : 1];
+    __shared__ __align__(16) float s_model[kLearn ? kMlpW2 + kMlpOut : 4];
     __shared__ __align__(16) float s_w2s[kLearn ? kMlpOut * kMlpHid : 4];
     // the features of the tile's blocks (lane-shared scoring)
     __shared__ float s_x[kLearn == 1 ? (kMaxTileBlocks / 4) * kMlpIn : 1];
@@ -382,15 +384,22 @@ __global__ __launch_bounds__(kThreads) void stats_kernel(CompressArgs a) {
     const bool learned = kLearn != 0;  // the variant is PCOMP_SELECT_LEARNED
     copy_size_ctx(a.ctx, s_C);
     // lanes read different weights at once: LDS serves those reads without the constant cache's
-    // serialisation (read before the first tile's barrier)
-    if (kLearn) {
-        for (uint32_t i = tid; i < (uint32_t)(kMlpW2 + kMlpOut); i += kThreads)
-            s_model[i] = c_model[i < (uint32_t)kMlpW2 ? i : i + kMlpOut * kMlpHid];
-        for (uint32_t i = tid; i < (uint32_t)(kMlpOut * kMlpHid); i += kThreads) {
-            const uint32_t k = i / kMlpHid, j = (i % kMlpHid) ^ (k << 2);
-            s_w2s[i] = c_model[kMlpW2 + k * kMlpHid + j];
+    // serialisation. Copied in 16-byte quads (W2 moves quad by quad: quad j of row k to j ^ k);
+    // read after the first tile's barrier. One tile per workgroup: copied while that tile's
+    // loads are in flight.
+    auto fill_model = [&]() {
+        constexpr uint32_t kQ1 = (kMlpW2 + kMlpOut) / 4, kQ2 = kMlpOut * kMlpHid / 4, kRow = kMlpHid / 4;
+        const float4 *src = (const float4 *)c_model;
+        for (uint32_t i = tid; i < kQ1 + kQ2; i += kThreads) {
+            if (i < kQ1) {  // W1, b1, then b2 (which follows W2 in the parameters)
+                ((float4 *)s_model)[i] = src[i < kMlpW2 / 4 ? i : i + kQ2];
+            } else {
+                const uint32_t o = i - kQ1, k = o / kRow, jq = (o % kRow) ^ k;
+                ((float4 *)s_w2s)[o] = src[kMlpW2 / 4 + k * kRow + jq];
+            }
         }
-    }
+    };
+    if (kLearn && kPersist) fill_model();
     const uint32_t span = kPair ? 2 : 1;
     for (uint64_t gt0 = a.tile_lo + span * blockIdx.x; gt0 < a.tile_hi; gt0 = kPersist ? gt0 + gridDim.x : a.tile_hi) {
         const uint32_t half = kPair ? tid / kPairBlocks : 0;
@@ -435,6 +444,7 @@ __global__ __launch_bounds__(kThreads) void stats_kernel(CompressArgs a) {
                 if (have[h]) first[h] = tile_commit<W>(tr[h], stg[h], s_raw + h * region);
             s_val = half ? first[1] : first[0];
         } else if (sd.rows) {
+            if (kLearn && !kPersist) fill_model();
             s_val = stage_tile_tm<W>(sd, v0, nvt, s_raw);
         } else if (kPersist) {
             s_val = stage_tile<W>(sd.data, v0, nvt, s_raw);
@@ -442,6 +452,7 @@ __global__ __launch_bounds__(kThreads) void stats_kernel(CompressArgs a) {
             const TileRef tr = tile_ref<W>(sd, v0, nvt);
             Staged stg;
             tile_fetch(tr, stg);
+            if (kLearn) fill_model();
             s_val = tile_commit<W>(tr, stg, s_raw);
         }
         __syncthreads();
