@@ -296,6 +296,27 @@ def decompress32(stream: torch.Tensor) -> torch.Tensor:
     return out[:n]
 
 
+class CompressorTransposed(Compressor):
+    """Reusable buffers for time-major blocking of same-shaped matrices [n_mat, rows, cols]
+    (``pcomp_compress_transposed``; no allocation per call)."""
+
+    def __init__(self, shape, dtype: torch.dtype, block_len: int, variant: int, device="cuda"):
+        n_mat, rows, cols = (int(v) for v in shape)
+        _require(rows > 0 and cols > 0, "rows and cols are positive")
+        super().__init__(n_mat * rows * cols, dtype, block_len, variant, device=device)
+        self.shape = (n_mat, rows, cols)
+
+    def __call__(self, x: torch.Tensor) -> None:
+        _require(_is_values(x) and tuple(x.shape) == self.shape and _DT[x.dtype] == self.w and
+                 x.device == self.out.device, "x is a contiguous CUDA tensor of the compressor's shape and dtype")
+        n_mat, rows, cols = self.shape
+        rc = lib().pcomp_compress_transposed(ctypes.c_void_p(x.data_ptr()), n_mat, rows, cols, self.w, self.L,
+                                             self.variant, ctypes.c_void_p(self.out.data_ptr()), self.out.numel(),
+                                             ctypes.c_void_p(self.size.data_ptr()),
+                                             ctypes.c_void_p(self.ws.data_ptr()), self.ws.numel(), _stream_handle())
+        _check(rc, "pcomp_compress_transposed")
+
+
 def compress_transposed(x: torch.Tensor, block_len: int, variant: int = 0) -> torch.Tensor:
     """Time-major blocking of matrices x [n_mat, rows, cols] (e.g. camera events [events,
     pixels, samples]): the stream of their transposes, read without a transposed copy

@@ -42,6 +42,8 @@ static_assert(kFeatWords * 4 * kMaxTileBlocks <= kTileBytes, "features must fit 
 
 struct CompressArgs {
     const SegDesc *segs;        // device table of the batch, or nullptr: the one segment is `one`
+    uint32_t xcd_tiles;         // tiles in XCD order (xcd_order): the time-major gathers of nearby
+                                // tiles read the same lines of the caller's matrices
     const uint32_t *tile_seg;   // plan index of the segment of every global tile (batch)
     const uint32_t *user_seg;   // plan index of every segment, in the caller's order (batch)
     SegDesc one;
@@ -401,7 +403,8 @@ __global__ __launch_bounds__(kThreads) void stats_kernel(CompressArgs a) {
     };
     if (kLearn && kPersist) fill_model();
     const uint32_t span = kPair ? 2 : 1;
-    for (uint64_t gt0 = a.tile_lo + span * blockIdx.x; gt0 < a.tile_hi; gt0 = kPersist ? gt0 + gridDim.x : a.tile_hi) {
+    const uint32_t wg = a.xcd_tiles ? xcd_order(blockIdx.x, gridDim.x) : blockIdx.x;
+    for (uint64_t gt0 = a.tile_lo + span * wg; gt0 < a.tile_hi; gt0 = kPersist ? gt0 + gridDim.x : a.tile_hi) {
         const uint32_t half = kPair ? tid / kPairBlocks : 0;
         const uint64_t gt = gt0 + half;
         const bool valid = gt < a.tile_hi;
@@ -823,7 +826,8 @@ __global__ __launch_bounds__(kThreads) void pack_kernel(CompressArgs a) {
     const bool fixed0 = (variant == 0 || variant == 8);
     copy_size_ctx(a.ctx, s_C);
     __syncthreads();  // the size tables are read before the first barrier of a tile
-    for (uint64_t gt = a.tile_lo + blockIdx.x; gt < a.tile_hi; gt = kPersist ? gt + gridDim.x : a.tile_hi) {
+    const uint32_t wg = a.xcd_tiles ? xcd_order(blockIdx.x, gridDim.x) : blockIdx.x;
+    for (uint64_t gt = a.tile_lo + wg; gt < a.tile_hi; gt = kPersist ? gt + gridDim.x : a.tile_hi) {
         uint32_t sj;
         const SegDesc sd = seg_of(a, gt, sj);
         const Layout &lo = sd.lo;
@@ -1085,6 +1089,7 @@ int launch_compress_table(const SegDesc *segs, const uint32_t *tile_seg, const u
     const WsLayout wl = ws_layout(n_tiles, n_segs, tile_lo, tile_hi, L);
     uint8_t *wsb = (uint8_t *)ws;
     a.segs = segs;
+    a.xcd_tiles = (!segs && one.rows) ? 1u : 0u;
     a.tile_seg = tile_seg;
     a.user_seg = user_seg;
     a.one = one;

@@ -724,7 +724,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(W == 4
     __syncthreads();
     // Tiles tile, tile + grid, ...: the next tile's arrays and words are started while this one
     // is merged and stored, and the index entries one tile further ahead.
-    uint64_t tile = blockIdx.x;
+    // time-major: tiles in XCD order, so that the scattered stores of nearby tiles meet in one L2
+    uint64_t tile = kTm ? xcd_order(blockIdx.x, gridDim.x) : blockIdx.x;
     if (tile >= lo.n_tiles) return;
     BlockRaw raw = load_raw<W>(a.in, lo, fixed, tile);
     TileSpan span = tile_span(a.in, lo, pw, tile);

@@ -201,6 +201,15 @@ __device__ __forceinline__ const typename Elem<W>::T *stage_tile(const uint8_t *
     return (const V *)(s_bytes + head);
 }
 
+// Workgroups are dispatched to the 8 XCDs (each with its own L2) in turn: workgroup b runs on
+// XCD b mod 8. xcd_order(b, n) renumbers the n workgroups of a launch so that each XCD takes one
+// contiguous run of the numbers, and tiles next to each other share an L2 (a bijection of
+// [0, n)).
+__device__ __forceinline__ uint32_t xcd_order(uint32_t b, uint32_t n) {
+    const uint32_t x = b & 7, q = n >> 3, r = n & 7;
+    return x * q + (x < r ? x : r) + (b >> 3);
+}
+
 // A pointer into LDS, as the compiler sees it: a staged tile chosen among several buffers can
 // lose that address space, and its reads would then take flat addressing.
 template <typename T>
