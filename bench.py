@@ -64,7 +64,9 @@ def parse():
     ap.add_argument("--stress-bytes", type=float, default=float(1 << 32),
                     help="bytes of the stress decompression leg (0 skips it)")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the latency, time-major, integrated and Poly+LZMA legs")
+                    help="skip the latency, time-major, 32-bit-word, integrated and Poly+LZMA legs")
+    ap.add_argument("--extras", default="latency,time_major,words32,integrated,poly_lzma",
+                    help="which of those legs to run (comma list)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB device to device three times (reference for the HBM byte counters)")
     return ap.parse_args()
@@ -595,11 +597,16 @@ def main():
                                            "place_kernel, pack_kernel"),
         "paper_reference": PAPER_REFERENCE,
     }
-    if not args.no_extras:
+    extras = set() if args.no_extras else set(args.extras.split(","))
+    if "latency" in extras:
         res["latency_tiny"] = latency_leg()
+    if "time_major" in extras:
         res["time_major"] = time_major_leg(x, L, variant)
+    if "words32" in extras:
         res["words32"] = words32_leg(x, L)
+    if "integrated" in extras:
         res["integrated"] = integrated_leg(x)
+    if "poly_lzma" in extras:
         res["poly_lzma"] = poly_lzma_leg([e for e in x[:400].cpu()], L, variant)
     del comp, out, stream
     torch.cuda.empty_cache()
