@@ -208,7 +208,8 @@ def batch_leg(n_events: int, reps: int):
     """Uneven camera events (shapes 1855x40, 2048x96, 11328x128; u16 or u32; noise sigma U(2,20);
     pulse fraction U(0,5%)) as one batch: block lengths and grid from the autotuner, the
     compression captured in one HIP graph, per-block class by the plain method (class 0), by
-    exhaustive search, and by the shipped learned selector. The streams are written back to back
+    exhaustive search, and by the shipped learned selector (on the exhaustive leg's block lengths
+    and grid). The streams are written back to back
     (one file, offsets on the device). At 50,000 events the input is ~86 GB, so decompression
     writes back into the input tensors: after the timed runs every segment is overwritten with
     0x5A, decoded once more, and its weighted 64-bit byte sum compared with the one taken before
@@ -229,8 +230,12 @@ def batch_leg(n_events: int, reps: int):
     ref = _weighted_sums(segs, weights)
     learn.use_selector()
     res = {"workload": "%d uneven camera events, %.3f GB (u16 and u32 mixed)" % (n_events, nbytes / 1e9)}
+    tuned = {}
     for name, v in (("plain", 0), ("exhaustive", pc.SELECT_EXHAUSTIVE), ("learned", pc.SELECT_LEARNED)):
-        t = tune.autotune(segs, v)
+        # the learned selector runs on the exhaustive leg's stream configuration (block lengths and
+        # grid), so that its ratio loss is the selector's alone
+        t = tuned["exhaustive"] if name == "learned" else tune.autotune(segs, v)
+        tuned[name] = t
         b = pc.Batch(segs, block_len=t["block_len"], variant=v, grid=t["grid"])
         gr = b.capture()
         dec = pc.BatchDecoder(b, segs, grid=t["grid"])
