@@ -47,7 +47,8 @@
  *   range[]   w bytes per block, B - 1
  *   class[]   u8 per block            (flags bit 0)
  *   ne[]      u8 per block, u16 if L > 255 (flags bit 1; bit 2 = u16)
- *   padding to 8 bytes, then the payload: u64 words, block after block.
+ *   padding to 8 bytes, then the payload: u64 words, block after block
+ *   (flags bit 3: 32-bit words instead, see pcomp_compress32).
  *   tile_blocks = the largest power of two P <= 256 with P * L * w <= 16384.
  */
 #ifndef PCOMP_H
