@@ -74,6 +74,34 @@ __device__ __forceinline__ const AtlasEntry32 *entry32(const DevTables &T, const
     return E + r;
 }
 
+// Consecutive words of the series from the cycle form: the entry of word i, then of i + 1, ...
+// without a division per word (entry mu + lam - 1 is followed by entry mu, V values further on).
+struct Cursor32 {
+    const AtlasEntry32 *E;
+    uint32_t idx, cyc, tot, mu, V;
+    __device__ __forceinline__ Cursor32(const DevTables &T, const BaseDesc32 &D, uint32_t i) {
+        E = T.ent32 + D.off;
+        mu = D.mu;
+        V = D.V;
+        tot = (uint32_t)D.mu + D.lam;
+        if (i < tot) {
+            idx = i;
+            cyc = 0;
+        } else {
+            cyc = udiv_small(i - D.mu, D.lam);
+            idx = i - cyc * D.lam;
+        }
+    }
+    __device__ __forceinline__ const AtlasEntry32 &entry() const { return E[idx]; }
+    __device__ __forceinline__ uint32_t q() const { return E[idx].q + cyc * V; }
+    __device__ __forceinline__ void next() {
+        if (++idx == tot) {
+            idx = mu;
+            cyc++;
+        }
+    }
+};
+
 // Stores the values of one tile, staged in LDS at the same offsets within 16-byte chunks as
 // they take in global memory (value 0 at byte (out + v0 W) mod 16): whole chunks as 16-byte
 // stores, the partial chunks at the ends value by value, so no byte outside the tile is written.
@@ -216,21 +244,31 @@ __global__ __launch_bounds__(kThreads) void w32_pack_kernel(W32Args a) {
         }
     } else if (nw) {
         // the series: word i = (r'_{i-1} B^{p_i} + its p_i digits) R_i + r_i, where the value
-        // after those digits is split as r_i = x mod R_i here and r'_i = x div R_i in word i + 1
+        // after those digits is split as r_i = x mod R_i here and r'_i = x div R_i in word i + 1.
+        // Lane g packs a run of consecutive words and carries r'_i from one to the next; only
+        // the run's first word divides its predecessor's split value.
         const BaseDesc32 &D = a.T.desc32[B];
         const uint32_t Bu = (uint32_t)B;
-        for (uint32_t i = g; i < nw; i += G) {
-            uint32_t q;
-            const AtlasEntry32 *e = entry32(a.T, D, i, q);
-            uint32_t body = 0;
-            if (i > 0) {
+        const uint32_t run = udiv_small(nw + G - 1, G);
+        const uint32_t w0 = g * run, w1 = w0 + run < nw ? w0 + run : nw;
+        if (w0 < w1) {
+            Cursor32 cur(a.T, D, w0);
+            uint32_t top = 0;  // r'_{i-1}
+            if (w0 > 0) {
                 uint32_t qp;
-                const AtlasEntry32 *ep = entry32(a.T, D, i - 1, qp);
-                body = get(qp + ep->p) / ep->R;  // r'_{i-1}
+                const AtlasEntry32 *ep = entry32(a.T, D, w0 - 1, qp);
+                top = get(qp + ep->p) / ep->R;
             }
-            const uint32_t p = e->p, R = e->R;
-            for (uint32_t kk = 0; kk < p; kk++) body = body * Bu + get(q + kk);
-            dst[i] = body * R + get(q + p) % R;
+            for (uint32_t i = w0; i < w1; i++) {
+                const AtlasEntry32 &e = cur.entry();
+                const uint32_t q = cur.q(), p = e.p, R = e.R;
+                uint32_t body = top;
+                for (uint32_t kk = 0; kk < p; kk++) body = body * Bu + get(q + kk);
+                const uint32_t x = get(q + p);
+                top = x / R;
+                dst[i] = body * R + (x - top * R);
+                cur.next();
+            }
         }
     }
 }
@@ -358,25 +396,37 @@ __global__ __launch_bounds__(kThreads) void w32_decompress_kernel(W32DecArgs a) 
                     }
                 }
             } else {
+                // lane g decodes a run of consecutive words: the value split between two of them
+                // is rebuilt from what the lane holds (r_{i-1} from the bottom of word i - 1,
+                // r'_{i-1} left on top of word i); only the run's first word reads its predecessor
                 const BaseDesc32 &D = a.T.desc32[B];
                 const double rB = D.rB, hB = 0.5 * rB, Bf = (double)B;
-                for (uint32_t i = g; i < nw; i += G) {
-                    uint32_t q;
-                    const AtlasEntry32 *e = entry32(a.T, D, i, q);
-                    uint32_t r;
-                    double x = digit_off((double)src[i], e->rR, 0.5 * e->rR, (double)e->R, r);  // r_i
-                    const uint32_t p = e->p;
-                    for (uint32_t kk = p; kk-- > 0;) {
-                        uint32_t d;
-                        x = digit_off(x, rB, hB, Bf, d);
-                        if (q + kk < Lb) s_out[q + kk] = (V)(vmin + d);
+                const uint32_t run = udiv_small(nw + G - 1, G);
+                const uint32_t w0 = g * run, w1 = w0 + run < nw ? w0 + run : nw;
+                if (w0 < w1) {
+                    Cursor32 cur(a.T, D, w0);
+                    uint32_t r_prev = 0, R_prev = 1;
+                    if (w0 > 0) {
+                        uint32_t qp;
+                        const AtlasEntry32 *ep = entry32(a.T, D, w0 - 1, qp);
+                        digit_off((double)src[w0 - 1], ep->rR, 0.5 * ep->rR, (double)ep->R, r_prev);
+                        R_prev = ep->R;
                     }
-                    if (i > 0) {  // what is left is r'_{i-1}: with r_{i-1} from word i - 1, the split value
-                        uint32_t qp, rp;
-                        const AtlasEntry32 *ep = entry32(a.T, D, i - 1, qp);
-                        digit_off((double)src[i - 1], ep->rR, 0.5 * ep->rR, (double)ep->R, rp);
-                        const uint32_t j = qp + ep->p;
-                        if (j < Lb) s_out[j] = (V)(vmin + (uint32_t)x * ep->R + rp);
+                    for (uint32_t i = w0; i < w1; i++) {
+                        const AtlasEntry32 &e = cur.entry();
+                        const uint32_t q = cur.q(), p = e.p;
+                        uint32_t r;
+                        double x = digit_off((double)src[i], e.rR, 0.5 * e.rR, (double)e.R, r);  // r_i
+                        for (uint32_t kk = p; kk-- > 0;) {
+                            uint32_t d;
+                            x = digit_off(x, rB, hB, Bf, d);
+                            if (q + kk < Lb) s_out[q + kk] = (V)(vmin + d);
+                        }
+                        // what is left is r'_{i-1}: with r_{i-1}, the value split before this word
+                        if (i > 0 && q - 1 < Lb) s_out[q - 1] = (V)(vmin + (uint32_t)x * R_prev + r_prev);
+                        r_prev = r;
+                        R_prev = e.R;
+                        cur.next();
                     }
                 }
             }
@@ -420,10 +470,10 @@ int launch_compress32(const void *d_in, const Layout &lo, int variant, void *d_o
     a.tile_words = (uint32_t *)(wsb + wl.tile_words);
     a.prefix = (uint64_t *)(wsb + wl.prefix);
     a.out_size = d_out_size;
-    w32_begin_kernel<<<1, 1, 0, st>>>(a.err);
     const uint64_t nt = lo.n_tiles;
+    if (nt > 0x7FFFFFFFull) return PCOMP_EINVAL;  // one workgroup per tile
+    w32_begin_kernel<<<1, 1, 0, st>>>(a.err);
     if (nt) {
-        if (nt > 0x7FFFFFFFull) return PCOMP_EINVAL;
         const uint32_t grid = (uint32_t)nt;
         if (lo.w == 1)
             w32_stats_kernel<1><<<grid, kThreads, 0, st>>>(a);
