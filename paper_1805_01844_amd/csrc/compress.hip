@@ -359,9 +359,17 @@ constexpr uint32_t kPairBlocks = kThreads / 2;
 // 16-byte chunks that a staged tile of tile_bytes may cover (its first value need not be aligned)
 __host__ __device__ inline uint32_t pair_region(uint32_t tile_bytes) { return (tile_bytes + 15) / 16 + 1; }
 // kLearn: 0 = no learned selector; 1 = learned, the lanes of a block share its network (tiles of
-// at most kMaxTileBlocks / 4 blocks); 2 = learned, one thread scores a block (larger tiles).
+// at most kMaxTileBlocks / 4 blocks); 2 = learned, one thread scores a block (larger tiles);
+// 3 = as 1 for tiles of at most kL3Blocks blocks, with the parameters, features and hidden units
+// in the tile's LDS once its values are read, so that the learned instance keeps the LDS and
+// the occupancy (8 wavefronts per SIMD) of the others.
+constexpr uint32_t kL3Blocks = 16;
+constexpr uint32_t kL3H = 0, kL3X = kL3H + kL3Blocks * kMlpHid, kL3W2 = (kL3X + kL3Blocks * kMlpIn + 3) & ~3u,
+                   kL3Model = kL3W2 + kMlpOut * kMlpHid;  // offsets in floats
+static_assert(4 * (kL3Model + kMlpW2 + kMlpOut) <= kTileBytes, "the selector's LDS fits the tile buffer");
 template <int W, bool kPersist, int kLearn, bool kPair = false>
-__global__ __launch_bounds__(kThreads) void stats_kernel(CompressArgs a) {
+__global__ __launch_bounds__(kThreads)
+__attribute__((amdgpu_waves_per_eu(kLearn == 3 && !kPersist ? (W == 4 ? 6 : 8) : 1))) void stats_kernel(CompressArgs a) {
     typedef typename Elem<W>::T V;
     __shared__ uint4 s_one[kPair ? 1 : kTileBytes / 16 + 1];
     extern __shared__ uint4 s_pair[];  // kPair: two regions of pair_region(tile bytes) chunks
@@ -374,8 +382,8 @@ __global__ __launch_bounds__(kThreads) void stats_kernel(CompressArgs a) {
     // the selector's parameters, per workgroup: W1, b1 and b2 (at kMlpW2) in s_model; W2 in s_w2s,
     // row k holding W2[k][j] at column j ^ 4k, so that the 16 lanes that score the 16 classes read
     // their rows' quads j .. j + 3 from 16 different bank groups
-    __shared__ __align__(16) float s_model[kLearn ? kMlpW2 + kMlpOut : 4];
-    __shared__ __align__(16) float s_w2s[kLearn ? kMlpOut * kMlpHid : 4];
+    __shared__ __align__(16) float s_model[kLearn == 1 || kLearn == 2 ? kMlpW2 + kMlpOut : 4];
+    __shared__ __align__(16) float s_w2s[kLearn == 1 || kLearn == 2 ? kMlpOut * kMlpHid : 4];
     // the features of the tile's blocks (lane-shared scoring)
     __shared__ float s_x[kLearn == 1 ? (kMaxTileBlocks / 4) * kMlpIn : 1];
 
@@ -389,19 +397,23 @@ __global__ __launch_bounds__(kThreads) void stats_kernel(CompressArgs a) {
     // serialisation. Copied in 16-byte quads (W2 moves quad by quad: quad j of row k to j ^ k);
     // read after the first tile's barrier. One tile per workgroup: copied while that tile's
     // loads are in flight.
+    float *const m_model = kLearn == 3 ? (float *)s_raw + kL3Model : s_model;
+    float *const m_w2s = kLearn == 3 ? (float *)s_raw + kL3W2 : s_w2s;
+    float *const m_x = kLearn == 3 ? (float *)s_raw + kL3X : s_x;
     auto fill_model = [&]() {
         constexpr uint32_t kQ1 = (kMlpW2 + kMlpOut) / 4, kQ2 = kMlpOut * kMlpHid / 4, kRow = kMlpHid / 4;
         const float4 *src = (const float4 *)c_model;
         for (uint32_t i = tid; i < kQ1 + kQ2; i += kThreads) {
             if (i < kQ1) {  // W1, b1, then b2 (which follows W2 in the parameters)
-                ((float4 *)s_model)[i] = src[i < kMlpW2 / 4 ? i : i + kQ2];
+                ((float4 *)m_model)[i] = src[i < kMlpW2 / 4 ? i : i + kQ2];
             } else {
                 const uint32_t o = i - kQ1, k = o / kRow, jq = (o % kRow) ^ k;
-                ((float4 *)s_w2s)[o] = src[kMlpW2 / 4 + k * kRow + jq];
+                ((float4 *)m_w2s)[o] = src[kMlpW2 / 4 + k * kRow + jq];
             }
         }
     };
-    if (kLearn && kPersist) fill_model();
+    constexpr bool kModelAhead = kLearn == 1 || kLearn == 2;  // parameters in LDS of their own
+    if (kModelAhead && kPersist) fill_model();
     const uint32_t span = kPair ? 2 : 1;
     const uint32_t wg = a.xcd_tiles ? xcd_order(blockIdx.x, gridDim.x) : blockIdx.x;
     for (uint64_t gt0 = a.tile_lo + span * wg; gt0 < a.tile_hi; gt0 = kPersist ? gt0 + gridDim.x : a.tile_hi) {
@@ -447,7 +459,7 @@ __global__ __launch_bounds__(kThreads) void stats_kernel(CompressArgs a) {
                 if (have[h]) first[h] = tile_commit<W>(tr[h], stg[h], s_raw + h * region);
             s_val = half ? first[1] : first[0];
         } else if (sd.rows) {
-            if (kLearn && !kPersist) fill_model();
+            if (kModelAhead && !kPersist) fill_model();
             s_val = stage_tile_tm<W>(sd, v0, nvt, s_raw);
         } else if (kPersist) {
             s_val = stage_tile<W>(sd.data, v0, nvt, s_raw);
@@ -455,7 +467,7 @@ __global__ __launch_bounds__(kThreads) void stats_kernel(CompressArgs a) {
             const TileRef tr = tile_ref<W>(sd, v0, nvt);
             Staged stg;
             tile_fetch(tr, stg);
-            if (kLearn) fill_model();
+            if (kModelAhead) fill_model();
             s_val = tile_commit<W>(tr, stg, s_raw);
         }
         __syncthreads();
@@ -543,20 +555,24 @@ __global__ __launch_bounds__(kThreads) void stats_kernel(CompressArgs a) {
         // longer needed); otherwise the features go through LDS and one thread per block scores it.
         // Both keep every sum's order, so the scores are the same bits.
         int pred = 0;
-        if (kLearn == 1) {
+        if (kLearn == 1 || kLearn == 3) {
+            if (kLearn == 3) {  // the tile's values are read: its LDS takes the selector's data
+                __syncthreads();
+                fill_model();
+            }
             if (live)
                 for (uint32_t f = g; f < (uint32_t)kMlpIn; f += G)
-                    s_x[blk * kMlpIn + f] = block_feature(f, hist.w, Lb, vmin, vmax);
+                    m_x[blk * kMlpIn + f] = block_feature(f, hist.w, Lb, vmin, vmax);
             __syncthreads();
             // hidden unit j of block b at b * kMlpHid + (j ^ 4 (b mod 4)): the four blocks scored
             // by one wave read their quads from four bank groups
-            float *s_h = (float *)s_raw;
+            float *s_h = (float *)s_raw + kL3H;
             if (live) {
-                const float *xb = s_x + blk * kMlpIn;
+                const float *xb = m_x + blk * kMlpIn;
                 for (uint32_t j = g; j < (uint32_t)kMlpHid; j += G) {
-                    float acc = s_model[kMlpB1 + j];
+                    float acc = m_model[kMlpB1 + j];
 #pragma unroll
-                    for (int i = 0; i < kMlpIn; i++) acc = __builtin_fmaf(s_model[kMlpW1 + j * kMlpIn + i], xb[i], acc);
+                    for (int i = 0; i < kMlpIn; i++) acc = __builtin_fmaf(m_model[kMlpW1 + j * kMlpIn + i], xb[i], acc);
                     s_h[blk * kMlpHid + (j ^ ((blk & 3) << 2))] = acc > 0.0f ? acc : 0.0f;
                 }
             }
@@ -564,8 +580,8 @@ __global__ __launch_bounds__(kThreads) void stats_kernel(CompressArgs a) {
             for (uint32_t q = tid; q < nbt * kMlpOut; q += kThreads) {  // 16-lane groups stay whole
                 const uint32_t sb = q / kMlpOut, k = q % kMlpOut;
                 const float4 *hq = (const float4 *)(s_h + sb * kMlpHid);
-                const float4 *wq = (const float4 *)(s_w2s + k * kMlpHid);
-                float acc = s_model[kMlpW2 + k];  // b2[k]
+                const float4 *wq = (const float4 *)(m_w2s + k * kMlpHid);
+                float acc = m_model[kMlpW2 + k];  // b2[k]
 #pragma unroll 4
                 for (uint32_t jq = 0; jq < (uint32_t)kMlpHid / 4; jq++) {
                     const float4 h = hq[jq ^ (sb & 3)], w = wq[jq ^ k];
@@ -1036,7 +1052,12 @@ void launch_tiles(bool stats, bool persist, uint32_t grid, size_t dyn, const Com
     const bool learned = b.variant == PCOMP_SELECT_LEARNED;
     if (stats && !learned && !persist && tile_blocks == kPairBlocks) {  // pairs of tiles, one lane per block
         stats_kernel<W, false, 0, true><<<(grid + 1) / 2, kThreads, 2 * 16 * pair_region(tile_bytes), st>>>(b);
-    } else if (stats && learned && tile_blocks && tile_blocks <= kMaxTileBlocks / 4) {  // all tiles have tile_blocks
+    } else if (stats && learned && tile_blocks && tile_blocks <= kL3Blocks) {  // all tiles have tile_blocks
+        if (persist)
+            stats_kernel<W, true, 3><<<grid, kThreads, 0, st>>>(b);
+        else
+            stats_kernel<W, false, 3><<<grid, kThreads, 0, st>>>(b);
+    } else if (stats && learned && tile_blocks && tile_blocks <= kMaxTileBlocks / 4) {
         if (persist)
             stats_kernel<W, true, 1><<<grid, kThreads, 0, st>>>(b);
         else
