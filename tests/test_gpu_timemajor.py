@@ -61,6 +61,19 @@ def test_ragged_and_wide_time_major(pc, orc):
     _case(pc, orc, x1.contiguous(), 7, 8, "tiny")
 
 
+def test_time_major_more_shapes(pc, orc):
+    # u8 and u32 matrices, many small matrices in one tile, tiles that start and end inside a
+    # column, ragged last blocks
+    g = torch.Generator().manual_seed(11)
+    x8 = torch.randint(0, 256, (3, 100, 32), generator=g, dtype=torch.int32).to(torch.uint8)
+    _case(pc, orc, x8, 37, EXH, "u8 rows of 32")
+    x32 = torch.randint(0, 1 << 31, (2, 70, 12), generator=g, dtype=torch.int64).to(torch.uint32)
+    _case(pc, orc, x32, 50, 0, "u32 rows of 12")
+    xs = torch.randint(0, 4000, (40, 64, 8), generator=g, dtype=torch.int32).to(torch.uint16)
+    for L, v in ((5, EXH), (64, 8), (1000, 3)):
+        _case(pc, orc, xs, L, v, "u16 small matrices")
+
+
 def test_time_major_shape_mismatch_is_reported(pc, orc):
     x = datagen.camera_events(2, seed=3).cuda()
     s = pc.compress_transposed(x, 40, EXH)
