@@ -164,6 +164,53 @@ __device__ __forceinline__ void pack_adv_slow(const DevTables &T, uint64_t base,
     }
 }
 
+// Advanced part whose base is outside the tables, packed by a group of at least 8 lanes: the
+// group walks the series once into its registers (SlowWindow) and lane i0 packs a run of
+// consecutive words with the entries read from the lanes holding them; one division of the
+// value split between two words gives r_i (its remainder by R_i) and r'_i (the quotient, on top
+// of word i + 1), and the run's first word takes r'_{i-1} from the value before it. Digits are
+// read in increasing order. Returns false, with nothing written, when the series has no period
+// within the window. Every lane of the group calls it.
+template <typename Get>
+__device__ __forceinline__ bool pack_adv_window(const DevTables &T, uint64_t base, uint32_t n, uint32_t nwords,
+                                                uint32_t i0, uint32_t G, uint64_t *dst, Get get) {
+    const SlowBase sb = slow_base(T, base);
+    const SlowWindow w = slow_window(sb, n, nwords, G < 64 ? G : 64);
+    if (!w.ok) return false;
+    const uint32_t run = udiv_small(nwords + G - 1, G);
+    const uint32_t w0 = min(i0 * run, nwords), w1 = min(w0 + run, nwords);
+    uint32_t j, c;  // entry and periods of word w0 - 1 + k (of word 0 for the first lane)
+    window_index(w, w0 ? w0 - 1 : 0, j, c);
+    uint64_t rp = 0;  // r'_{i-1}
+    for (uint32_t k = 0; k <= run; k++) {  // the same count on every lane (entries are read across lanes)
+        const uint64_t E = window_entry(w, j);
+        const uint64_t R = E & kWinR;
+        const uint32_t p = (uint32_t)((E >> 48) & 3) + 1;
+        const uint32_t q = (uint32_t)(E >> 50) + c * w.V;
+        const uint32_t i = w0 + k - 1;
+        if (k == 0) {
+            if (w0 > 0 && w0 < w1) {  // the value split between words w0 - 1 and w0
+                const uint64_t x = q + p < n ? get(q + p) : 0;
+                rp = R <= x ? udiv53(x, R) : 0;
+            }
+        } else if (i < w1) {  // digits in increasing order (the absent ones of a last word are 0)
+            uint64_t acc = rp;
+            const uint32_t real = q < n ? min(p, n - q) : 0;
+            for (uint32_t m = 0; m < p; m++) acc = acc * base + (m < real ? get(q + m) : 0);
+            const uint64_t x = q + p < n ? get(q + p) : 0;
+            uint64_t r = x, top = 0;
+            if (R <= x) {
+                top = udiv53(x, R);
+                r = x - top * R;
+            }
+            dst[i] = acc * R + r;
+            rp = top;
+        }
+        if (k > 0 || w0 > 0) window_next(w, j, c);
+    }
+    return true;
+}
+
 // Digits of a threshold block's excess list (d - T for the values d >= T, in data order)
 // read straight from the staged tile, for tiles whose excess lists do not fit the compaction
 // buffer. Lane c of the block's group holds in pre[c] the number of excess values before its
@@ -214,8 +261,11 @@ struct ExcessReader {
 template <bool Wide, typename Get>
 __device__ __forceinline__ void pack_part(const DevTables &T, const SizeCtx &C, uint64_t base, uint32_t n, int fam,
                                           uint32_t nwords, uint32_t i0, uint32_t G, uint64_t *dst, Get get) {
-    if (nwords == 0 || i0 >= nwords) return;
+    if (nwords == 0) return;
     const PartBase pb = resolve_base<Wide>(T, C, base);
+    // a base outside the tables (u32 data only): the whole group walks its series together
+    if (Wide && fam && !pb.D && G >= 8 && pack_adv_window(T, base, n, nwords, i0, G, dst, get)) return;
+    if (i0 >= nwords) return;
     if (!fam) {
         // Sec. 3.1 Eq. (2): word i holds digits i*k .. i*k+k-1, the first at the highest power
         for (uint32_t i = i0; i < nwords; i += G) dst[i] = horner_word<Wide>(pb, 0, i * pb.k, pb.k, n, get);
@@ -649,7 +699,13 @@ __attribute__((amdgpu_waves_per_eu(kLearn == 3 && !kPersist ? (W == 4 ? 6 : 8) :
             } else if (B > 1) {
                 const uint32_t kb = k_fast(s_C, B);
                 w0 = udiv_small(Lb + kb - 1, kb);
-                w8 = adv_words_k<(W == 4)>(T, s_C, Lb, B, kb, L);
+                if (W == 4 && kLearn == 0 && G >= 8 && Lb > kb && atlas_index(B) < 0) {
+                    // a base outside the tables: the group walks its series together
+                    const uint32_t width = G < 64 ? G : 64;
+                    const SlowWindow sw = slow_window(slow_base(T, B), Lb, 0xFFFFFFFFu, width);
+                    if (sw.ok) w8 = window_words(sw, Lb, width);
+                }
+                if (!w8) w8 = adv_words_k<(W == 4)>(T, s_C, Lb, B, kb, L);
             }
             // keys (words << 8 | id) in 32 bits: a block of at most 2^16 values has fewer than 2^24 words
             uint32_t k32 = w0 << 8;

@@ -148,11 +148,62 @@ __device__ __forceinline__ void unpack_adv_slow(const DevTables &T, uint64_t bas
 // Decodes words i0, i0+G, ... of one part (main digits or excess list) into dst[0 .. n);
 // `add` is added to every digit (the block minimum for plain blocks); src(i) is word i of the
 // part.
+// Advanced part whose base is outside the tables, decoded by a group of at least 8 lanes: the
+// group walks the series once into its registers (SlowWindow) and lane i0 decodes a run of
+// consecutive words with the entries read from the lanes holding them, rebuilding the value
+// split between two words from r_{i-1} and the part left on top of word i; the value split after
+// the run comes from the next run's first word. Returns false, with nothing written, when the
+// series has no period within the window. Every lane of the group calls it.
+template <typename V, typename Src, typename Dst>
+__device__ __forceinline__ bool unpack_adv_window(const DevTables &T, uint64_t base, uint32_t n, uint32_t nwords,
+                                                  uint32_t i0, uint32_t G, Src src, Dst dst, uint32_t add) {
+    const SlowBase sb = slow_base(T, base);
+    const SlowWindow w = slow_window(sb, n, nwords, G < 64 ? G : 64);
+    if (!w.ok) return false;
+    const Magic mB = magic_dev(base);
+    const uint32_t run = udiv_small(nwords + G - 1, G);
+    const uint32_t w0 = min(i0 * run, nwords), w1 = min(w0 + run, nwords);
+    uint32_t j, c;  // entry and periods of word w0 + k
+    window_index(w, w0, j, c);
+    uint64_t r_prev = 0, R_prev = 1;
+    uint32_t q_end = 0;  // q + p of the previous word: the place of the value split after it
+    for (uint32_t k = 0; k <= run; k++) {  // the same count on every lane (entries are read across lanes)
+        const uint32_t i = w0 + k;
+        const uint64_t E = window_entry(w, j);
+        if (w0 < w1 && i <= w1 && i < nwords) {
+            const uint64_t R = E & kWinR;
+            const uint32_t p = (uint32_t)((E >> 48) & 3) + 1;
+            const uint32_t q = (uint32_t)(E >> 50) + c * w.V;
+            uint64_t r;
+            uint64_t X = udiv64_48(src(i), R, r);  // word = (r'_{i-1} B^p + digits) R + r
+            if (i < w1) {
+                for (int m = (int)p - 1; m >= 0; m--) {
+                    const uint64_t qq = div_magic(X, mB);
+                    if (q + (uint32_t)m < n) dst[q + m] = (V)((uint32_t)(X - qq * base) + add);
+                    X = qq;
+                }
+            } else {
+                for (uint32_t m = 0; m < p; m++) X = div_magic(X, mB);
+            }
+            // X is now r'_{i-1}, the top of the value split between words i - 1 and i
+            if (i > w0 && q_end < n) dst[q_end] = (V)((uint32_t)(X * R_prev + r_prev) + add);
+            r_prev = r;
+            R_prev = R;
+            q_end = q + p;
+        }
+        window_next(w, j, c);
+    }
+    return true;
+}
+
 template <typename V, bool Wide, bool kRuns, typename Src, typename Dst>
 __device__ __forceinline__ void unpack_part(const DevTables &T, const PartBase &pb, uint32_t n, int fam,
                                             uint32_t nwords, uint32_t i0, uint32_t G, Src src, Dst dst,
                                             uint32_t add) {
-    if (nwords == 0 || i0 >= nwords) return;
+    if (nwords == 0) return;
+    // a base outside the tables (u32 data only): the whole group walks its series together
+    if (Wide && kRuns && fam && !pb.D && unpack_adv_window<V>(T, pb.base, n, nwords, i0, G, src, dst, add)) return;
+    if (i0 >= nwords) return;
     auto put = [&](uint32_t j, uint32_t d) {
         if (j < n) dst[j] = (V)(d + add);
     };

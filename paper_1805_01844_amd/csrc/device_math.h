@@ -180,6 +180,114 @@ __device__ __forceinline__ uint32_t next_own_word(uint32_t wi, uint32_t i0, uint
     return wi <= i0 ? i0 : i0 + ((wi - i0 + G - 1) & ~(G - 1));
 }
 
+// The schedule of the series of a base outside the tables (Sec. 3.2), held in the registers of
+// a group of lanes that walk it in step. Every lane computes the same words, and after word t
+// lane g of the window (the group's first `width` lanes within the wavefront) holds the entry of
+// word t - g: R_t | (p_t - 1) << 48 | q_t << 50. The state (p_t, R_t) fixes every later word, so
+// the first word whose state equals that of an earlier one, found by comparing it with every
+// held entry at once, closes the period: words from cs = t - lam on repeat every lam words, V
+// values further on. The walk stops there, at the part's last word, or with the window full
+// (ok false: the caller then walks the series lane by lane). Every lane of the window calls it
+// with the same arguments.
+struct SlowWindow {
+    uint64_t e;           // this lane's entry (all ones: none)
+    uint32_t seg, last;   // first lane of the window in the wavefront; newest word held (at lane seg)
+    uint32_t cs, lam, V;  // the period (lam = 0: none, every word of the part is held)
+    bool ok;
+};
+
+constexpr uint64_t kWinR = (1ull << 48) - 1;      // R of an entry
+constexpr uint64_t kWinState = (1ull << 50) - 1;  // R and p of an entry
+
+// 64 bits of lane `src` of the wavefront (an active lane).
+__device__ __forceinline__ uint64_t lane_read64(uint64_t v, uint32_t src) {
+    const int a = (int)(src << 2);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_bpermute(a, (int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_ds_bpermute(a, (int)(uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ SlowWindow slow_window(const SlowBase &sb, uint32_t n, uint32_t nwords, uint32_t width) {
+    SlowWindow w;
+    const uint32_t lane = __lane_id();
+    w.seg = lane & ~(width - 1);
+    const uint32_t gl = lane - w.seg;
+    const uint64_t wmask = (width >= 64 ? ~0ull : (1ull << width) - 1) << w.seg;
+    w.e = ~0ull;  // p - 1 = 3 is no entry's, so it matches nothing
+    w.last = 0;
+    w.cs = w.lam = w.V = 0;
+    w.ok = false;
+    uint64_t s = 1;
+    uint32_t q = 0;
+    for (uint32_t t = 0;; t++) {
+        uint32_t p;
+        uint64_t R;
+        slow_word_fast(sb, s, p, R);
+        const uint64_t E = R | ((uint64_t)(p - 1) << 48) | ((uint64_t)q << 50);
+        const uint64_t m = __ballot(((w.e ^ E) & kWinState) == 0) & wmask;
+        if (m) {  // lane g holds word t - 1 - g, and at most one held word has this state
+            const uint32_t g = (uint32_t)__builtin_ctzll(m >> w.seg);
+            w.lam = g + 1;
+            w.cs = t - w.lam;
+            w.V = q - (uint32_t)(lane_read64(w.e, w.seg + g) >> 50);
+        }
+        const uint64_t up = lane_read64(w.e, gl ? lane - 1 : lane);
+        w.e = gl ? up : E;
+        w.last = t;
+        if (m || q + p >= n || t + 1 >= nwords) {
+            w.ok = true;
+            break;
+        }
+        if (t + 1 >= width) break;
+        s = slow_next(sb, R);
+        q += p + 1;
+    }
+    return w;
+}
+
+// Entry of word i from a window: its index among the held words and the periods before it.
+__device__ __forceinline__ void window_index(const SlowWindow &w, uint32_t i, uint32_t &j, uint32_t &c) {
+    j = i;
+    c = 0;
+    if (w.lam && i > w.cs) {
+        c = udiv_small(i - w.cs, w.lam);
+        j = i - c * w.lam;
+    }
+}
+
+__device__ __forceinline__ uint64_t window_entry(const SlowWindow &w, uint32_t j) {
+    return lane_read64(w.e, w.seg + w.last - (j <= w.last ? j : w.last));
+}
+
+__device__ __forceinline__ void window_next(const SlowWindow &w, uint32_t &j, uint32_t &c) {
+    j++;
+    if (w.lam && j == w.cs + w.lam) {
+        j = w.cs;
+        c++;
+    }
+}
+
+// Word count of the series for n digits (1 + the first word t with q_t + p_t >= n) from a
+// window walked with no word limit: every held word of the period proposes the first of its
+// repeats that reaches n, and the window takes the least. Every lane of the window calls it.
+__device__ __forceinline__ uint32_t window_words(const SlowWindow &w, uint32_t n, uint32_t width) {
+    const uint32_t gl = __lane_id() - w.seg;
+    uint32_t best = 0xFFFFFFFFu;
+    if (gl <= w.last) {
+        const uint32_t j = w.last - gl;
+        const uint32_t reach = (uint32_t)(w.e >> 50) + (uint32_t)((w.e >> 48) & 3) + 1;  // q_j + p_j
+        if (reach >= n)
+            best = j;
+        else if (w.lam && j >= w.cs)
+            best = j + udiv_small(n - reach + w.V - 1, w.V) * w.lam;
+    }
+    for (uint32_t o = 1; o < width; o <<= 1) {
+        const uint32_t y = (uint32_t)__shfl_xor((int)best, (int)o, 64);
+        best = y < best ? y : best;
+    }
+    return best + 1;
+}
+
 // Word count of the series (Sec. 3.2) for n digits: walk it word by word. The carried base
 // s_t determines everything after word t, so once Brent's cycle search finds s_t = s_{t-lam}
 // the series repeats with period lam from there, consuming V = q_t - q_{t-lam} values per

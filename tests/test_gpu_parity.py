@@ -105,6 +105,50 @@ def test_wide_u32_bases_outside_tables(pc, orc):
         _check(pc, orc, x, 512, v, "wide_u32")
 
 
+def _series_span(B: int) -> int:
+    """mu + lam of the carried base of the Sec. 3.2 series of base B with 64-bit words (words
+    before the period plus its length), walked here in Python integers."""
+    k = 1
+    while B ** (k + 1) <= 1 << 64:
+        k += 1
+    Q = [(1 << 64) // B ** p for p in range(k + 1)]
+    s, seen = 1, {}
+    while s not in seen:
+        seen[s] = len(seen)
+        p = k if s <= Q[k] else k - 1
+        R = Q[p] // s
+        s = 1 if R >= B else -(-B // R)
+    return len(seen)
+
+
+@pytest.mark.parametrize("L", [128, 256, 512, 1024, 2048, 4096])
+def test_u32_series_periods_outside_tables(pc, orc, L):
+    # u32 blocks of bases outside the tables whose series repeat after 1 .. 250 words: lane
+    # groups of 8 to 256 lanes hold the period in their registers when it fits, and walk the
+    # series lane by lane when it does not; the last block is ragged
+    rng = np.random.default_rng(L)
+    spans = {}
+    while len(spans) < 24:
+        B = int(rng.integers((1 << 16) + 2, (1 << 32) + 1))
+        m = _series_span(B)
+        bucket = min(m.bit_length(), 8)
+        if sum(1 for v in spans.values() if v == bucket) < 4:
+            spans[B] = bucket
+    bases = list(spans)
+    nblk = max(24, 40000 // L)
+    x = np.empty(nblk * L, np.uint32)
+    for b in range(nblk):
+        B = bases[b % len(bases)]
+        lo = int(rng.integers(0, (1 << 32) - B + 1))
+        v = rng.integers(0, B, L, dtype=np.uint64)
+        v[rng.integers(0, L)] = 0
+        v[rng.integers(0, L)] = B - 1
+        x[b * L:(b + 1) * L] = (v + lo).astype(np.uint32)
+    x = torch.from_numpy(x[: nblk * L - 7].view(np.int32)).view(torch.uint32)
+    for v in (8, 9, 12, EXH):
+        _check(pc, orc, x, L, v, "u32_periods")
+
+
 def test_misaligned_input(pc, orc):
     base = datagen.camera_events(1, seed=9).reshape(-1).cuda()
     for off in (1, 3, 5):
