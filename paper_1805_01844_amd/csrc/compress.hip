@@ -188,10 +188,15 @@ __device__ __forceinline__ bool pack_adv_window(const DevTables &T, uint64_t bas
         const uint32_t p = (uint32_t)((E >> 48) & 3) + 1;
         const uint32_t q = (uint32_t)(E >> 50) + c * w.V;
         const uint32_t i = w0 + k - 1;
+        // a value below 2^32 divided by R < 2^48
+        auto split = [&](uint64_t x) -> uint64_t {
+            const double Rd = (double)R;
+            return (uint64_t)floor_div_f64((double)x, Rd, recip_f64(Rd));
+        };
         if (k == 0) {
             if (w0 > 0 && w0 < w1) {  // the value split between words w0 - 1 and w0
                 const uint64_t x = q + p < n ? get(q + p) : 0;
-                rp = R <= x ? udiv53(x, R) : 0;
+                rp = R <= x ? split(x) : 0;
             }
         } else if (i < w1) {  // digits in increasing order (the absent ones of a last word are 0)
             uint64_t acc = rp;
@@ -200,7 +205,7 @@ __device__ __forceinline__ bool pack_adv_window(const DevTables &T, uint64_t bas
             const uint64_t x = q + p < n ? get(q + p) : 0;
             uint64_t r = x, top = 0;
             if (R <= x) {
-                top = udiv53(x, R);
+                top = split(x);
                 r = x - top * R;
             }
             dst[i] = acc * R + r;

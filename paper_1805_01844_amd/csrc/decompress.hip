@@ -174,8 +174,13 @@ __device__ __forceinline__ bool unpack_adv_window(const DevTables &T, uint64_t b
             const uint64_t R = E & kWinR;
             const uint32_t p = (uint32_t)((E >> 48) & 3) + 1;
             const uint32_t q = (uint32_t)(E >> 50) + c * w.V;
-            uint64_t r;
-            uint64_t X = udiv64_48(src(i), R, r);  // word = (r'_{i-1} B^p + digits) R + r
+            uint64_t r, X;  // word = (r'_{i-1} B^p + digits) R + r
+            if (R == 1) {
+                X = src(i);
+                r = 0;
+            } else {
+                X = udiv64_rcp(src(i), R, recip_f64((double)R), r);
+            }
             if (i < w1) {
                 for (int m = (int)p - 1; m >= 0; m--) {
                     const uint64_t qq = div_magic(X, mB);

@@ -50,6 +50,46 @@ __device__ __forceinline__ uint64_t udiv64_48(uint64_t X, uint64_t R, uint64_t &
     return q;
 }
 
+// 1/d for 1 <= d < 2^53 to within a relative 2^-50: two Newton-Raphson steps
+// (r <- r + r (1 - d r), each squaring the relative error) from the hardware estimate.
+__device__ __forceinline__ double recip_f64(double d) {
+    double r = __builtin_amdgcn_rcp(d);
+    double e = __builtin_fma(-d, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    e = __builtin_fma(-d, r, 1.0);
+    return __builtin_fma(r, e, r);
+}
+
+// floor(a / d) for integers 0 <= a < 2^53 and 1 <= d < 2^50 held exactly in binary64, with
+// a / d < 2^48 and r = recip_f64(d). The product a r is within 1/4 of a / d, so its truncation
+// is floor(a / d) or one unit off, and the remainder a - q d (an integer of magnitude below 2d,
+// exact from one FMA) tells which way.
+__device__ __forceinline__ double floor_div_f64(double a, double d, double r) {
+    const double q = __builtin_trunc(a * r);
+    const double rem = __builtin_fma(-q, d, a);
+    return rem < 0.0 ? q - 1.0 : (rem >= d ? q + 1.0 : q);
+}
+
+// floor(X / R) and X mod R for any 64-bit X and 2 <= R < 2^48, with rR = recip_f64(R): the first
+// quotient, from X rounded to binary64 times rR, is within 2^14 of X / R, so the remainder it
+// leaves is below 2^62 in magnitude; a second product gives the rest to within one unit.
+__device__ __forceinline__ uint64_t udiv64_rcp(uint64_t X, uint64_t R, double rR, uint64_t &rem) {
+    uint64_t q = (uint64_t)((double)X * rR);
+    int64_t r = (int64_t)(X - q * R);
+    const int64_t q1 = (int64_t)__builtin_floor((double)r * rR);
+    r -= q1 * (int64_t)R;
+    q += (uint64_t)q1;
+    if (r < 0) {
+        r += (int64_t)R;
+        q--;
+    } else if ((uint64_t)r >= R) {
+        r -= (int64_t)R;
+        q++;
+    }
+    rem = (uint64_t)r;
+    return q;
+}
+
 // Magic numbers for a divisor d in [1, 2^32], computed on the device: m - 1 =
 // floor((2^l - d) 2^64 / d) by two 64-bit long-division steps on 32-bit limbs
 // (2^l - d < d <= 2^32, so every partial dividend fits 64 bits).
@@ -115,9 +155,11 @@ __device__ __forceinline__ uint32_t k_of(const DevTables &T, uint64_t B) {
     return lo;
 }
 
-// Constants of the series for a base outside the tables (2^16 + 1 < B <= 2^32).
+// Constants of the series for a base outside the tables (2^16 + 1 < B <= 2^32), also as
+// binary64 (every one below 2^48, so held exactly).
 struct SlowBase {
     uint64_t B, Qk, Qk1;
+    double Bd, Bm1d, Qkd, Qk1d;
     uint32_t k;
 };
 
@@ -137,19 +179,35 @@ __device__ __forceinline__ SlowBase slow_base(const DevTables &T, uint64_t B) {
     }
     sb.Qk = Q;
     sb.Qk1 = Qprev;
+    sb.Bd = (double)B;
+    sb.Bm1d = (double)(B - 1);
+    sb.Qkd = (double)Q;
+    sb.Qk1d = (double)Qprev;
     return sb;
 }
 
-// One word of the series for a base outside the tables without integer divides: every
-// floor(2^64 / B^p) is below 2^48 here (B > 2^16 + 1) and the carried base s is at most B.
-__device__ __forceinline__ void slow_word_fast(const SlowBase &sb, uint64_t s, uint32_t &p, uint64_t &R) {
-    p = (s <= sb.Qk) ? sb.k : sb.k - 1;
-    R = udiv53((p == sb.k) ? sb.Qk : sb.Qk1, s);
+// One word of the series for a base outside the tables, in binary64: every floor(2^64 / B^p)
+// is below 2^48 here (B > 2^16 + 1) and the carried base s is at most B <= 2^32, so
+// R = floor(Q_p / s) is a floor_div_f64 of exact integers.
+__device__ __forceinline__ void slow_word_f64(const SlowBase &sb, double s, uint32_t &p, double &R) {
+    const bool full = s <= sb.Qkd;
+    p = full ? sb.k : sb.k - 1;
+    R = floor_div_f64(full ? sb.Qkd : sb.Qk1d, s, recip_f64(s));
 }
 
-// The carried base of the next word, ceil(B / R).
+// The carried base of the next word, ceil(B / R) = floor((B - 1) / R) + 1 (1 for R >= B).
+__device__ __forceinline__ double slow_next_f64(const SlowBase &sb, double R) {
+    return R >= sb.Bd ? 1.0 : floor_div_f64(sb.Bm1d, R, recip_f64(R)) + 1.0;
+}
+
+__device__ __forceinline__ void slow_word_fast(const SlowBase &sb, uint64_t s, uint32_t &p, uint64_t &R) {
+    double Rd;
+    slow_word_f64(sb, (double)s, p, Rd);
+    R = (uint64_t)Rd;
+}
+
 __device__ __forceinline__ uint64_t slow_next(const SlowBase &sb, uint64_t R) {
-    return R >= sb.B ? 1 : udiv53(sb.B - 1, R) + 1;
+    return (uint64_t)slow_next_f64(sb, (double)R);
 }
 
 // Brent's cycle search over the carried base of the series (Sec. 3.2): s_t, the state of word
@@ -217,13 +275,13 @@ __device__ __forceinline__ SlowWindow slow_window(const SlowBase &sb, uint32_t n
     w.last = 0;
     w.cs = w.lam = w.V = 0;
     w.ok = false;
-    uint64_t s = 1;
+    double s = 1.0;
     uint32_t q = 0;
     for (uint32_t t = 0;; t++) {
         uint32_t p;
-        uint64_t R;
-        slow_word_fast(sb, s, p, R);
-        const uint64_t E = R | ((uint64_t)(p - 1) << 48) | ((uint64_t)q << 50);
+        double R;
+        slow_word_f64(sb, s, p, R);
+        const uint64_t E = (uint64_t)R | ((uint64_t)(p - 1) << 48) | ((uint64_t)q << 50);
         const uint64_t m = __ballot(((w.e ^ E) & kWinState) == 0) & wmask;
         if (m) {  // lane g holds word t - 1 - g, and at most one held word has this state
             const uint32_t g = (uint32_t)__builtin_ctzll(m >> w.seg);
@@ -239,7 +297,7 @@ __device__ __forceinline__ SlowWindow slow_window(const SlowBase &sb, uint32_t n
             break;
         }
         if (t + 1 >= width) break;
-        s = slow_next(sb, R);
+        s = slow_next_f64(sb, R);
         q += p + 1;
     }
     return w;
