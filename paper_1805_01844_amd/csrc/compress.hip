@@ -708,7 +708,7 @@ __attribute__((amdgpu_waves_per_eu(kLearn == 3 && !kPersist ? (W == 4 ? 6 : 8) :
                     // a base outside the tables: the group walks its series together
                     const uint32_t width = G < 64 ? G : 64;
                     const SlowWindow sw = slow_window(slow_base(T, B), Lb, 0xFFFFFFFFu, width);
-                    if (sw.ok) w8 = window_words(sw, Lb, width);
+                    if (sw.ok) w8 = window_words(sw, Lb);
                 }
                 if (!w8) w8 = adv_words_k<(W == 4)>(T, s_C, Lb, B, kb, L);
             }
@@ -882,8 +882,10 @@ __global__ __launch_bounds__(kThreads) void place_kernel(CompressArgs a) {
 }
 
 // ---- launch 4: packing ----------------------------------------------------------------
+// u32 packing keeps six wavefronts per SIMD (at most 80 vector registers).
 template <int W, bool kPersist>
-__global__ __launch_bounds__(kThreads) void pack_kernel(CompressArgs a) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(W == 4 && !kPersist ? 6 : 1))) void pack_kernel(
+    CompressArgs a) {
     typedef typename Elem<W>::T V;
     __shared__ uint4 s_raw[kTileBytes / 16 + 1];
     __shared__ uint16_t s_cpre[kThreads];  // threshold blocks: excess values before each lane's chunk

@@ -239,18 +239,21 @@ __device__ __forceinline__ uint32_t next_own_word(uint32_t wi, uint32_t i0, uint
 }
 
 // The schedule of the series of a base outside the tables (Sec. 3.2), held in the registers of
-// a group of lanes that walk it in step. Every lane computes the same words, and after word t
-// lane g of the window (the group's first `width` lanes within the wavefront) holds the entry of
-// word t - g: R_t | (p_t - 1) << 48 | q_t << 50. The state (p_t, R_t) fixes every later word, so
-// the first word whose state equals that of an earlier one, found by comparing it with every
-// held entry at once, closes the period: words from cs = t - lam on repeat every lam words, V
-// values further on. The walk stops there, at the part's last word, or with the window full
-// (ok false: the caller then walks the series lane by lane). Every lane of the window calls it
-// with the same arguments.
+// a group of lanes that walk it in step. Every lane computes the same words; word t is held by
+// lane t mod width of the window (the group's first `width` lanes within the wavefront), in its
+// register t / width, as R_t | (p_t - 1) << 48 | q_t << 50. The state (p_t, R_t) fixes every later
+// word, so the first word whose state equals that of a held one, found by comparing it with
+// every held entry at once, closes the period: words from cs on repeat every lam words, V values
+// further on. The walk stops there, at the part's last word, or with the window full (ok false:
+// the caller then walks the series lane by lane). Every lane of the window calls it with the same
+// arguments.
+constexpr uint32_t kWinRegs = 4;  // entries per lane: periods up to 4 x width words are held
+
 struct SlowWindow {
-    uint64_t e;           // this lane's entry (all ones: none)
-    uint32_t seg, last;   // first lane of the window in the wavefront; newest word held (at lane seg)
-    uint32_t cs, lam, V;  // the period (lam = 0: none, every word of the part is held)
+    uint64_t e[kWinRegs];  // words gl, gl + width, ... of this lane gl (all ones: none)
+    uint32_t seg, shift;   // first lane of the window in the wavefront; log2(width)
+    uint32_t last;         // last word held
+    uint32_t cs, lam, V;   // the period (lam = 0: none, every word of the part is held)
     bool ok;
 };
 
@@ -269,9 +272,11 @@ __device__ __forceinline__ SlowWindow slow_window(const SlowBase &sb, uint32_t n
     SlowWindow w;
     const uint32_t lane = __lane_id();
     w.seg = lane & ~(width - 1);
+    w.shift = 31 - __clz(width);
     const uint32_t gl = lane - w.seg;
     const uint64_t wmask = (width >= 64 ? ~0ull : (1ull << width) - 1) << w.seg;
-    w.e = ~0ull;  // p - 1 = 3 is no entry's, so it matches nothing
+#pragma unroll
+    for (uint32_t r = 0; r < kWinRegs; r++) w.e[r] = ~0ull;  // p - 1 = 3 is no entry's, so it matches nothing
     w.last = 0;
     w.cs = w.lam = w.V = 0;
     w.ok = false;
@@ -282,21 +287,30 @@ __device__ __forceinline__ SlowWindow slow_window(const SlowBase &sb, uint32_t n
         double R;
         slow_word_f64(sb, s, p, R);
         const uint64_t E = (uint64_t)R | ((uint64_t)(p - 1) << 48) | ((uint64_t)q << 50);
-        const uint64_t m = __ballot(((w.e ^ E) & kWinState) == 0) & wmask;
-        if (m) {  // lane g holds word t - 1 - g, and at most one held word has this state
-            const uint32_t g = (uint32_t)__builtin_ctzll(m >> w.seg);
-            w.lam = g + 1;
-            w.cs = t - w.lam;
-            w.V = q - (uint32_t)(lane_read64(w.e, w.seg + g) >> 50);
+        // the held word of the same state, if any (at most one: the walk stops at the first)
+        uint32_t hit = 0;  // 1 + its word index and its q
+#pragma unroll
+        for (uint32_t r = 0; r < kWinRegs; r++)
+            if (((w.e[r] ^ E) & kWinState) == 0) hit = 1u | ((gl + (r << w.shift)) << 1) | ((uint32_t)(w.e[r] >> 50) << 16);
+        const uint64_t m = __ballot(hit != 0) & wmask;
+        if (m) {
+            const uint32_t h = (uint32_t)__shfl((int)hit, (int)(w.seg + __builtin_ctzll(m >> w.seg)), 64);
+            w.cs = (h >> 1) & 0x7FFF;
+            w.lam = t - w.cs;
+            w.V = q - (h >> 16);
         }
-        const uint64_t up = lane_read64(w.e, gl ? lane - 1 : lane);
-        w.e = gl ? up : E;
+        // word t goes to lane t mod width, register t / width
+        const uint32_t slot = t >> w.shift;
+        if (gl == (t & (width - 1))) {
+#pragma unroll
+            for (uint32_t r = 0; r < kWinRegs; r++) w.e[r] = r == slot ? E : w.e[r];
+        }
         w.last = t;
         if (m || q + p >= n || t + 1 >= nwords) {
             w.ok = true;
             break;
         }
-        if (t + 1 >= width) break;
+        if (t + 1 >= (kWinRegs << w.shift)) break;
         s = slow_next_f64(sb, R);
         q += p + 1;
     }
@@ -313,8 +327,18 @@ __device__ __forceinline__ void window_index(const SlowWindow &w, uint32_t i, ui
     }
 }
 
+// Entry of held word j (every lane of the window calls it; each may ask for another word).
 __device__ __forceinline__ uint64_t window_entry(const SlowWindow &w, uint32_t j) {
-    return lane_read64(w.e, w.seg + w.last - (j <= w.last ? j : w.last));
+    j = j <= w.last ? j : w.last;
+    const uint32_t src = w.seg + (j & ((1u << w.shift) - 1)), slot = j >> w.shift;
+    uint64_t v = 0;
+#pragma unroll
+    for (uint32_t r = 0; r < kWinRegs; r++) {
+        if ((r << w.shift) > w.last) break;  // the same on every lane of the window
+        const uint64_t x = lane_read64(w.e[r], src);
+        v = r == slot ? x : v;
+    }
+    return v;
 }
 
 __device__ __forceinline__ void window_next(const SlowWindow &w, uint32_t &j, uint32_t &c) {
@@ -328,18 +352,22 @@ __device__ __forceinline__ void window_next(const SlowWindow &w, uint32_t &j, ui
 // Word count of the series for n digits (1 + the first word t with q_t + p_t >= n) from a
 // window walked with no word limit: every held word of the period proposes the first of its
 // repeats that reaches n, and the window takes the least. Every lane of the window calls it.
-__device__ __forceinline__ uint32_t window_words(const SlowWindow &w, uint32_t n, uint32_t width) {
+__device__ __forceinline__ uint32_t window_words(const SlowWindow &w, uint32_t n) {
     const uint32_t gl = __lane_id() - w.seg;
     uint32_t best = 0xFFFFFFFFu;
-    if (gl <= w.last) {
-        const uint32_t j = w.last - gl;
-        const uint32_t reach = (uint32_t)(w.e >> 50) + (uint32_t)((w.e >> 48) & 3) + 1;  // q_j + p_j
+#pragma unroll
+    for (uint32_t r = 0; r < kWinRegs; r++) {
+        const uint32_t j = gl + (r << w.shift);
+        if (j > w.last) continue;
+        const uint32_t reach = (uint32_t)(w.e[r] >> 50) + (uint32_t)((w.e[r] >> 48) & 3) + 1;  // q_j + p_j
+        uint32_t cand = 0xFFFFFFFFu;
         if (reach >= n)
-            best = j;
+            cand = j;
         else if (w.lam && j >= w.cs)
-            best = j + udiv_small(n - reach + w.V - 1, w.V) * w.lam;
+            cand = j + udiv_small(n - reach + w.V - 1, w.V) * w.lam;
+        best = cand < best ? cand : best;
     }
-    for (uint32_t o = 1; o < width; o <<= 1) {
+    for (uint32_t o = 1; o < (1u << w.shift); o <<= 1) {
         const uint32_t y = (uint32_t)__shfl_xor((int)best, (int)o, 64);
         best = y < best ? y : best;
     }
