@@ -472,7 +472,9 @@ __device__ __forceinline__ void decode_tile(const DevTables &T, const uint8_t *i
         const uint64_t base_off = span.base, next_off = span.next;
         uint64_t key = 0;
         bool adv = false;
-        uint32_t nw_own = 0;
+        uint32_t nw_own = 0, cat = 0;
+        constexpr uint32_t kExSh = kRuns ? 16 : 18, kCatSh = 31, kBadSh = kRuns ? 55 : 54;
+        constexpr uint64_t kNwMask = kRuns ? 0xFFFF : 0x3FFFF, kExMask = kRuns ? 0x7FFF : 0x3FFFF;
         if (tid < nbt) {
             const uint64_t gb = b0 + tid;
             const uint32_t bmin = raw.bmin, rng = raw.rng;
@@ -494,27 +496,34 @@ __device__ __forceinline__ void decode_tile(const DevTables &T, const uint8_t *i
             S.nwm[tid] = (uint16_t)nwm;
             adv = ok && (c >> 3);
             nw_own = nw;
-            // words (18 bits: a tile holds at most 2^14 values), excess values (18), then for
-            // word-by-word decoding the words of advanced blocks (18), else basic blocks (9) and
-            // advanced blocks (9); invalid blocks (9)
-            key = (uint64_t)nw | ((uint64_t)(ok && t ? ne : 0) << 18) | ((uint64_t)(ok ? 0 : 1) << 54);
+            cat = (adv ? 2u : 0u) + (ok && t ? 1u : 0u);
+            // Word-by-word decoding: words (18 bits; at most two per value, 2^15 in a tile),
+            // excess values (18), the words of advanced blocks (18), invalid blocks (9).
+            // Lane groups (at most 32 blocks a tile): words (16), excess values (15), the blocks
+            // of each kind (basic, basic threshold, advanced, advanced threshold: 6 each),
+            // invalid blocks (6).
+            key = (uint64_t)nw | ((uint64_t)(ok && t ? ne : 0) << kExSh) | ((uint64_t)(ok ? 0 : 1) << kBadSh);
             if (kRuns)
-                key |= ((uint64_t)(adv ? 0 : 1) << 36) | ((uint64_t)(adv ? 1 : 0) << 45);
+                key |= 1ull << (kCatSh + 6 * cat);
             else
                 key |= (uint64_t)(adv ? nw : 0) << 36;
         }
         uint64_t tot;
         const uint64_t ex = wg_excl_scan64(key, S.red64, &tot);
-        const uint32_t tile_words = (uint32_t)(tot & 0x3FFFF), extot = (uint32_t)((tot >> 18) & 0x3FFFF);
-        const uint32_t n_basic = (uint32_t)((tot >> 36) & 0x1FF), n_bad = (uint32_t)(tot >> 54);
+        const uint32_t tile_words = (uint32_t)(tot & kNwMask), extot = (uint32_t)((tot >> kExSh) & kExMask);
+        const uint32_t n_bad = (uint32_t)(tot >> kBadSh);
         // word-by-word decoding takes the words of basic blocks first (slots 0 .. w_basic - 1),
         // then those of advanced blocks, each family in block order
         const uint32_t w_basic = tile_words - (uint32_t)((tot >> 36) & 0x3FFFF);
         if (tid < nbt) {
-            S.off[tid] = (uint32_t)(ex & 0x3FFFF);
-            S.exoff[tid] = (uint16_t)((ex >> 18) & 0x3FFFF);
+            S.off[tid] = (uint32_t)(ex & kNwMask);
+            S.exoff[tid] = (uint16_t)((ex >> kExSh) & kExMask);
             if (kRuns) {
-                S.perm[adv ? n_basic + (uint32_t)((ex >> 45) & 0x1FF) : (uint32_t)((ex >> 36) & 0x1FF)] = (uint8_t)tid;
+                // lane groups take the blocks kind by kind, so that a wavefront's groups mostly
+                // run the same code
+                uint32_t first = 0;
+                for (uint32_t k = 0; k < cat; k++) first += (uint32_t)(tot >> (kCatSh + 6 * k)) & 0x3F;
+                S.perm[first + ((uint32_t)(ex >> (kCatSh + 6 * cat)) & 0x3F)] = (uint8_t)tid;
             } else {  // advanced words before the block, and the block of each of its slots
                 const uint32_t o = (uint32_t)(ex & 0x3FFFF), ap = (uint32_t)((ex >> 36) & 0x3FFFF);
                 S.advw[tid] = (uint16_t)ap;
@@ -830,7 +839,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(W == 4
         uint64_t pw;
         int fixed;
         const bool ok = off < a.in_size && (off & 7) == 0 && read_layout(s, a.in_size - off, lo, pw, fixed) &&
-                        lo.w == W && lo.n == sd.lo.n && lo.L == sd.lo.L && lo.flags == sd.lo.flags;
+                        lo.w == W && lo.n == sd.lo.n && lo.L == sd.lo.L && lo.flags == sd.lo.flags &&
+                        (kThreads / lo.tile_blocks >= kRunLanes) == kRuns;
         if (!ok) {
             if (threadIdx.x == 0) set_status(a.status, PCOMP_ECORRUPT);
             continue;
