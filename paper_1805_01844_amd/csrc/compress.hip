@@ -936,6 +936,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(W == 4
         // its word offset, its place among the tile's excess values and its lane group (basic
         // blocks first, then advanced ones, so that wavefronts mostly run one family's code).
         uint64_t key = 0;
+        const bool fine = tb <= 32;
+        const uint32_t cbits = fine ? 6 : 9;
+        uint32_t kcat = 0;
         if (tid < nbt) {
             const uint64_t gb = b0 + tid;
             const uint64_t r = (gt - a.tile_lo) * tb + tid;
@@ -954,22 +957,26 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(W == 4
             if (lo.flags & kFlagClass) so[lo.off_class + gb] = (uint8_t)c;
             if (lo.flags & kFlagNe)
                 put_le(so + lo.off_ne + gb * ((lo.flags & kFlagNe16) ? 2 : 1), ne, (lo.flags & kFlagNe16) ? 2 : 1);
-            const bool adv = c >> 3;
-            // words (18 bits: a tile holds at most 2^14 values), excess values (18), basic
-            // blocks (9), advanced blocks (9)
-            key = (uint64_t)nw | ((uint64_t)(!fixed0 && (c & 7) ? ne : 0) << 18) | ((uint64_t)(adv ? 0 : 1) << 36) |
-                  ((uint64_t)(adv ? 1 : 0) << 45);
+            // words (16 bits: at most one per value, 2^14 in a tile), excess values (15), then the
+            // blocks of each kind: for tiles of at most 32 blocks basic, basic threshold,
+            // advanced and advanced threshold (6 bits each), else basic and advanced (9 each)
+            const uint32_t cat = fine ? (uint32_t)((c >> 3) * 2 + ((c & 7) ? 1 : 0)) : (uint32_t)(c >> 3);
+            key = (uint64_t)nw | ((uint64_t)(!fixed0 && (c & 7) ? ne : 0) << 16) | (1ull << (31 + cbits * cat));
+            kcat = cat;
         }
         if (!kPersist && !tm) s_val = tile_commit<W>(tr, stg, s_raw);
         uint64_t tot;
         const uint64_t exs = wg_excl_scan64(key, s_red64, &tot);
-        const uint32_t total = (uint32_t)(tot & 0x3FFFF), extot = (uint32_t)((tot >> 18) & 0x3FFFF);
+        const uint32_t total = (uint32_t)(tot & 0xFFFF), extot = (uint32_t)((tot >> 16) & 0x7FFF);
         if (tid < nbt) {
-            const uint32_t n_basic = (uint32_t)((tot >> 36) & 0x1FF);
-            s_off[tid] = (uint16_t)(exs & 0x3FFFF);
-            s_exoff[tid] = (uint16_t)((exs >> 18) & 0x3FFFF);
-            s_perm[(key >> 45) & 1 ? n_basic + (uint32_t)((exs >> 45) & 0x1FF) : (uint32_t)((exs >> 36) & 0x1FF)] =
-                (uint8_t)tid;
+            // lane groups take the blocks kind by kind, so that a wavefront's groups mostly run
+            // the same code
+            const uint32_t cmask = (1u << cbits) - 1;
+            uint32_t first = 0;
+            for (uint32_t k = 0; k < kcat; k++) first += (uint32_t)(tot >> (31 + cbits * k)) & cmask;
+            s_off[tid] = (uint16_t)(exs & 0xFFFF);
+            s_exoff[tid] = (uint16_t)((exs >> 16) & 0x7FFF);
+            s_perm[first + ((uint32_t)(exs >> (31 + cbits * kcat)) & cmask)] = (uint8_t)tid;
         }
         if (tid == 0) s_off[nbt] = (uint16_t)total;
         __syncthreads();
