@@ -1,9 +1,11 @@
 // device_math.h -- integer building blocks of the HIP kernels (device code).
 //
 // Everything here is exact integer arithmetic. Division by a block constant uses
-// Granlund-Montgomery multiply-high magic numbers (PLDI 1994, Fig. 4.1); the few
-// divisions by data-dependent values (word counts, the schedule of a base outside the
-// precomputed table) go through the compiler's integer division.
+// Granlund-Montgomery multiply-high magic numbers (PLDI 1994, Fig. 4.1); divisions by
+// data-dependent values (the schedule of a base outside the precomputed tables) are binary64
+// quotients of exact integers with a one-unit correction from the exact remainder, and small
+// ones (word counts, cycle positions) a binary32 reciprocal product; there is no integer
+// divide on the device.
 #pragma once
 #include "pcomp_internal.h"
 
