@@ -457,15 +457,28 @@ __attribute__((amdgpu_waves_per_eu(kLearn == 3 && !kPersist ? (W == 4 ? 6 : 8) :
     float *const m_x = kLearn == 3 ? (float *)s_raw + kL3X : s_x;
     auto fill_model = [&]() {
         constexpr uint32_t kQ1 = (kMlpW2 + kMlpOut) / 4, kQ2 = kMlpOut * kMlpHid / 4, kRow = kMlpHid / 4;
+        static_assert(kQ1 + kQ2 <= 3 * kThreads, "three quads per thread");
         const float4 *src = (const float4 *)c_model;
-        for (uint32_t i = tid; i < kQ1 + kQ2; i += kThreads) {
-            if (i < kQ1) {  // W1, b1, then b2 (which follows W2 in the parameters)
-                ((float4 *)m_model)[i] = src[i < kMlpW2 / 4 ? i : i + kQ2];
-            } else {
-                const uint32_t o = i - kQ1, k = o / kRow, jq = (o % kRow) ^ k;
-                ((float4 *)m_w2s)[o] = src[kMlpW2 / 4 + k * kRow + jq];
-            }
-        }
+        // quad i of the LDS copy: W1, b1, then b2 (which follows W2 in the parameters), then W2
+        // with the quads of row k rotated by k
+        auto quad = [&](uint32_t i) -> float4 {
+            if (i < kQ1) return src[i < kMlpW2 / 4 ? i : i + kQ2];
+            const uint32_t o = i - kQ1, k = o / kRow, jq = (o % kRow) ^ k;
+            return src[kMlpW2 / 4 + k * kRow + jq];
+        };
+        auto put = [&](uint32_t i, float4 v) {
+            if (i < kQ1)
+                ((float4 *)m_model)[i] = v;
+            else if (i < kQ1 + kQ2)
+                ((float4 *)m_w2s)[i - kQ1] = v;
+        };
+        // all three loads are in flight before the first store
+        const uint32_t i0 = tid, i1 = tid + kThreads, i2 = tid + 2 * kThreads;
+        const float4 z = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        const float4 v0 = quad(i0), v1 = quad(i1), v2 = i2 < kQ1 + kQ2 ? quad(i2) : z;
+        put(i0, v0);
+        put(i1, v1);
+        put(i2, v2);
     };
     constexpr bool kModelAhead = kLearn == 1 || kLearn == 2;  // parameters in LDS of their own
     if (kModelAhead && kPersist) fill_model();
