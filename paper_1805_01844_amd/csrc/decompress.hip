@@ -627,12 +627,13 @@ __device__ __forceinline__ void decode_tile(const DevTables &T, const uint8_t *i
                 return fam ? resolve_base<(W == 4)>(T, S.C, base) : basic_base(S.C, base);
             };
             V *vals = s_val + (size_t)blk * L;
-            if (t == 0) {
-                unpack_part<V, (W == 4), kRuns>(T, base_of(B), Lb, fam, nwb, g, G, src, vals, S.min[blk]);
-            } else {
-                const uint64_t Th = 1ull << (bitlen64(B - 1) - t);
-                const uint32_t nwm = S.nwm[blk];
-                unpack_part<V, (W == 4), kRuns>(T, base_of(Th + 1), Lb, fam, nwm, g, G, src, vals, S.min[blk]);
+            // the main part: the block's only part, or for threshold classes the digits min(d, T)
+            // in base T + 1 (one call for both, so that groups of the two kinds in a wavefront
+            // run it together)
+            const uint64_t Th = t ? 1ull << (bitlen64(B - 1) - t) : 0;
+            const uint32_t nwm = t ? (uint32_t)S.nwm[blk] : nwb;
+            unpack_part<V, (W == 4), kRuns>(T, base_of(t ? Th + 1 : B), Lb, fam, nwm, g, G, src, vals, S.min[blk]);
+            if (t) {
                 const PartBase pe = base_of(B - Th);
                 auto esrc = [&](uint32_t i) -> uint64_t { return word_at(w0 + nwm + i); };
                 if (exc_lds)
