@@ -1045,16 +1045,16 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(W == 4
         }
         if (live && nw) {
             uint64_t *dst = (uint64_t *)(so + lo.off_payload) + base_off + s_off[blk];
-            // digit readers: pack_part asks only for digits of the part (j < its length)
-            if (tcls == 0) {
-                pack_part<(W == 4)>(T, s_C, B, Lb, fam, nw, g, G, dst,
-                                    [&](uint32_t j) -> uint64_t { return (uint64_t)((uint32_t)bv[j] - bmin); });
-            } else {
-                const uint32_t Th32 = (uint32_t)Th;  // T <= 2^31
-                pack_part<(W == 4)>(T, s_C, Th + 1, Lb, fam, nwm, g, G, dst, [&](uint32_t j) -> uint64_t {
-                    const uint32_t d = (uint32_t)bv[j] - bmin;
-                    return (uint64_t)(d < Th32 ? d : Th32);
-                });
+            // digit readers: pack_part asks only for digits of the part (j < its length). The main
+            // part: the block's only part, or for threshold classes the digits min(d, T) in base
+            // T + 1 (one call for both, so that groups of the two kinds in a wavefront run it
+            // together; T <= 2^31, and no digit exceeds the bound of a plain block)
+            const uint32_t Th32 = tcls ? (uint32_t)Th : 0xFFFFFFFFu;
+            pack_part<(W == 4)>(T, s_C, tcls ? Th + 1 : B, Lb, fam, tcls ? nwm : nw, g, G, dst, [&](uint32_t j) -> uint64_t {
+                const uint32_t d = (uint32_t)bv[j] - bmin;
+                return (uint64_t)(d < Th32 ? d : Th32);
+            });
+            if (tcls) {
                 if (compact) {
                     const V *ex = s_ex + s_exoff[blk];
                     pack_part<(W == 4)>(T, s_C, B - Th, ne, fam, nw - nwm, g, G, dst + nwm,
