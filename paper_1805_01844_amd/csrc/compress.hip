@@ -271,16 +271,57 @@ __device__ __forceinline__ void pack_part(const DevTables &T, const SizeCtx &C, 
     // a base outside the tables (u32 data only): the whole group walks its series together
     if (Wide && fam && !pb.D && G >= 8 && pack_adv_window(T, base, n, nwords, i0, G, dst, get)) return;
     if (i0 >= nwords) return;
-    if (!fam) {
-        // Sec. 3.1 Eq. (2): word i holds digits i*k .. i*k+k-1, the first at the highest power
+    if (!fam && (G >= 8 || Wide)) {
+        // Sec. 3.1 Eq. (2): word i holds digits i*k .. i*k+k-1, the first at the highest power.
+        // Groups of 8 or more lanes take the words in turn (consecutive lanes read nearby digits;
+        // such tiles take their blocks kind by kind, so families rarely share a wavefront), and
+        // so does u32 data (whose packing keeps its registers).
         for (uint32_t i = i0; i < nwords; i += G) dst[i] = horner_word<Wide>(pb, 0, i * pb.k, pb.k, n, get);
         return;
     }
+    if (!Wide && G < 8 && (!fam || pb.D)) {
+        // Sec. 3.1 Eq. (2) and the Sec. 3.2 series in one loop, so that groups of both families
+        // in a wavefront (tiles of 64 blocks or more) run it together. A basic word i holds
+        // digits i k .. i k + k - 1, the first at the highest power (R = 1, no split value); an
+        // advanced word i is (r'_{i-1} B^{p_i} + digits) R_i + r_i with its state from the cycle
+        // form. Lane i0 packs a run of consecutive words: one division of the value split between
+        // two advanced words gives both r_i (its remainder by R_i, at the bottom of word i) and
+        // r'_i (the quotient, on top of word i + 1).
+        const uint32_t run = udiv_small(nwords + G - 1, G);
+        const uint32_t w0 = i0 * run, w1 = w0 + run < nwords ? w0 + run : nwords;
+        if (w0 >= w1) return;
+        uint32_t q = 0, p = pb.k;
+        uint64_t R = 1;
+        Magic mR = {0, 0, 0};  // division by 1
+        auto word = [&](uint32_t i) {
+            if (fam) {
+                const AtlasEntry *e = adv_entry(T, *pb.D, i, q);
+                p = e->p;
+                R = e->R;
+                mR = e->mR;
+            } else {
+                q = i * pb.k;
+            }
+        };
+        uint64_t rp = 0;  // r'_{i-1}
+        if (fam && w0 > 0) {  // the value split between words w0 - 1 and w0
+            word(w0 - 1);
+            rp = div_magic(get(q + p), mR);
+        }
+        for (uint32_t i = w0; i < w1; i++) {
+            word(i);
+            // digits are read in increasing order (the excess-list reader relies on it)
+            const uint64_t acc = horner_word<Wide>(pb, (uint32_t)rp, q, p, n, get);
+            const uint64_t x = fam && q + p < n ? get(q + p) : 0;
+            const uint64_t qx = div_magic(x, mR);
+            dst[i] = acc * R + (x - qx * R);
+            rp = qx;
+        }
+        return;
+    }
     if (pb.D) {
-        // Sec. 3.2 series: word i = (r'_{i-1} B^{p_i} + digits) R_i + r_i, state from the cycle
-        // form. Lane i0 of the group packs a run of consecutive words: one division of the value
-        // split between two words gives both r_i (its remainder by R_i, at the bottom of word i)
-        // and r'_i (the quotient, on top of word i + 1).
+        // groups of 8 or more lanes and u32 data: the Sec. 3.2 series alone (the same runs, with
+        // fewer registers held)
         const BaseDesc &D = *pb.D;
         const uint32_t run = udiv_small(nwords + G - 1, G);
         const uint32_t w0 = i0 * run, w1 = w0 + run < nwords ? w0 + run : nwords;
@@ -295,7 +336,6 @@ __device__ __forceinline__ void pack_part(const DevTables &T, const SizeCtx &C, 
         }
         for (uint32_t i = w0; i < w1; i++) {
             if (i > w0) e = adv_entry(T, D, i, q);
-            // digits are read in increasing order (the excess-list reader relies on it)
             const uint64_t acc = horner_word<Wide>(pb, (uint32_t)rp, q, e->p, n, get);
             const uint64_t x = q + e->p < n ? get(q + e->p) : 0;
             const uint64_t qx = div_magic(x, e->mR);
