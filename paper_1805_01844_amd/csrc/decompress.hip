@@ -304,19 +304,22 @@ __device__ __forceinline__ void unpack_word(const DevTables &T, const PartBase &
     auto put = [&](uint32_t j, uint32_t d) {
         if (j < n) dst[j] = (V)(d + add);
     };
-    if (!fam) {  // inverse of Sec. 3.1 Eq. (2)
-        peel_digits<Wide>(pb, X, i * pb.k, pb.k, put);
-        return;
-    }
-    if (pb.D) {  // Sec. 3.2: r'_{i-1} on top, p_i digits, r_i at the bottom
-        const BaseDesc &D = *pb.D;
-        uint32_t q;
-        const AtlasEntry *e = adv_entry(T, D, i, q);
-        const uint64_t qR = div_magic(X, e->mR);
-        const uint64_t r = X - qR * e->R;
-        const uint32_t p = e->p;
-        peel_digits<Wide>(pb, qR, q, p, put);
-        if (q + p < n && i + 1 < nwords) {  // the value split with the next word
+    if (!fam || pb.D) {
+        // the inverse of Sec. 3.1 Eq. (2) (k digits of word i) and of the Sec. 3.2 series
+        // (r'_{i-1} on top, p_i digits, r_i at the bottom) share the peeling, so that a
+        // wavefront holding words of both families runs it once
+        uint32_t q = i * pb.k, p = pb.k;
+        uint64_t digits = X, r = 0;
+        const AtlasEntry *e = nullptr;
+        if (fam) {
+            e = adv_entry(T, *pb.D, i, q);
+            digits = div_magic(X, e->mR);
+            r = X - digits * e->R;
+            p = e->p;
+        }
+        peel_digits<Wide>(pb, digits, q, p, put);
+        if (fam && q + p < n && i + 1 < nwords) {  // the value split with the next word
+            const BaseDesc &D = *pb.D;
             uint32_t q1;
             const AtlasEntry *e1 = adv_entry(T, D, i + 1, q1);
             const uint64_t Y = div_magic(src(i + 1), e1->mR);
